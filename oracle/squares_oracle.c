@@ -1,0 +1,227 @@
+/*
+ * CPU ORACLE for the Squares counter-based RNG (Widynski, "Squares: A Fast
+ * Counter-Based RNG", arXiv 2004.06278).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
+ * reference that the GPU library is checked against.  It shares no code,
+ * header, table or helper with the GPU library, and the GPU library never
+ * links, loads or calls it.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may use it.
+ *
+ * All arithmetic is on uint64_t, i.e. modulo 2^64 (C unsigned wraparound),
+ * which is the arithmetic the paper's C listings are written in.  Nothing
+ * here is blocked, fused, vectorised or reordered.
+ *
+ * Parity pins (what ties this file to the paper, not to itself) live in the
+ * CPU test suite: closed forms for key 0 and for sparse power-of-two keys
+ * worked by hand, the ctr = 0 reduction, the identity hi32(squares64) ==
+ * squares32, the Weyl identity, counter wrap, a bit-balance screen, and a
+ * mutation battery showing each plausible transcription mistake fails one
+ * of them.
+ */
+#include <stdint.h>
+#include <stddef.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------
+ * Building blocks of one round (Section 2, Algorithm; Section 3, Discussion)
+ * ------------------------------------------------------------------------ */
+
+/* Half-square step of a round: the low 64 bits of x*x, plus a Weyl term.
+ * Section 2 says only half of the square is formed; uint64_t keeps exactly
+ * that half. */
+static uint64_t half_square_plus(uint64_t x, uint64_t weyl)
+{
+    return x * x + weyl;
+}
+
+/* Circular shift by 32 bits after each square (Section 3): the random
+ * middle bits move to the low half for the next round. */
+static uint64_t rotate32(uint64_t x)
+{
+    return (x >> 32) | (x << 32);
+}
+
+/* The two Weyl terms (Section 2 and Section 3).  The Weyl sequence w += s is
+ * replaced by counter * key, so the first addend is ctr*key.  The second is
+ * (ctr+1)*key, which the Discussion introduces so that one of the two
+ * always carries non-zero digits. */
+static uint64_t weyl_y(uint64_t ctr, uint64_t key) { return ctr * key; }
+static uint64_t weyl_z(uint64_t ctr, uint64_t key) { return (ctr + 1u) * key; }
+
+/* Rounds alternate the two addends: odd rounds add y, even rounds add z
+ * (both listings: rounds 1..5 add y, z, y, z, y). */
+static uint64_t round_addend(int round, uint64_t y, uint64_t z)
+{
+    return (round % 2 == 1) ? y : z;
+}
+
+/* x entering round `last`, after rounds 1 .. last-1, each a half square plus
+ * addend followed by the rotation.  x starts as y (= ctr*key). */
+static uint64_t state_before_round(uint64_t y, uint64_t z, int last)
+{
+    uint64_t x = y;
+    for (int r = 1; r < last; ++r)
+        x = rotate32(half_square_plus(x, round_addend(r, y, z)));
+    return x;
+}
+
+/* ------------------------------------------------------------------------
+ * The two generators
+ * ------------------------------------------------------------------------ */
+
+/* squares32 (Section 2): four rounds; the output is the upper 32 bits of the
+ * fourth half square.  Argument order (ctr, key) follows the paper. */
+uint32_t oracle_squares32(uint64_t ctr, uint64_t key)
+{
+    const uint64_t y = weyl_y(ctr, key);
+    const uint64_t z = weyl_z(ctr, key);
+    const uint64_t x = state_before_round(y, z, 4);
+    const uint64_t r4 = half_square_plus(x, round_addend(4, y, z));
+    return (uint32_t)(r4 >> 32);
+}
+
+/* squares64 (Section 5): the fourth round's full 64-bit half square t is
+ * kept; after rotating it, a fifth round is squared and its upper 32 bits
+ * are XORed into t. */
+uint64_t oracle_squares64(uint64_t ctr, uint64_t key)
+{
+    const uint64_t y = weyl_y(ctr, key);
+    const uint64_t z = weyl_z(ctr, key);
+    const uint64_t x = state_before_round(y, z, 4);
+    const uint64_t t = half_square_plus(x, round_addend(4, y, z));
+    const uint64_t r5 = half_square_plus(rotate32(t), round_addend(5, y, z));
+    return t ^ (r5 >> 32);
+}
+
+/* Per-round trace for debugging and cross-checks: trace[r-1] is x right
+ * after round r's half square (before its rotation), r = 1..5. */
+void oracle_trace(uint64_t ctr, uint64_t key, uint64_t trace[5])
+{
+    const uint64_t y = weyl_y(ctr, key);
+    const uint64_t z = weyl_z(ctr, key);
+    uint64_t x = y;
+    for (int r = 1; r <= 5; ++r) {
+        trace[r - 1] = half_square_plus(x, round_addend(r, y, z));
+        x = rotate32(trace[r - 1]);
+    }
+}
+
+/* ------------------------------------------------------------------------
+ * Uniform conversions.  Section 5 reports floating point outputs of 53-bit
+ * precision but prints no formula.  The reading used here: the top 24 bits
+ * of a squares32 output scaled by 2^-24 (a float in [0,1)), and the top 53
+ * bits of a squares64 output scaled by 2^-53 (a double in [0,1)).  Both are
+ * exact: the integer fits the significand and the scale is a power of two.
+ * ------------------------------------------------------------------------ */
+float oracle_to_f32(uint32_t u)
+{
+    return (float)(u >> 8) * 0x1p-24f;
+}
+
+double oracle_to_f64(uint64_t u)
+{
+    return (double)(u >> 11) * 0x1p-53;
+}
+
+/* ------------------------------------------------------------------------
+ * Bulk forms over a counter range.  Element i uses counter ctr0 + i, taken
+ * modulo 2^64 (the counter is a 64-bit integer, Section 3), so a range that
+ * passes 2^64 - 1 continues at 0 with the same key.
+ * ------------------------------------------------------------------------ */
+
+/* Output kinds shared with the tests (values are part of the test contract,
+ * not taken from any other code). */
+enum { ORACLE_U32 = 0, ORACLE_F32 = 1, ORACLE_U64 = 2, ORACLE_F64 = 3 };
+
+void oracle_fill_u32(uint64_t key, uint64_t ctr0, uint64_t n, uint32_t *out)
+{
+    for (uint64_t i = 0; i < n; ++i)
+        out[i] = oracle_squares32(ctr0 + i, key);
+}
+
+void oracle_fill_u64(uint64_t key, uint64_t ctr0, uint64_t n, uint64_t *out)
+{
+    for (uint64_t i = 0; i < n; ++i)
+        out[i] = oracle_squares64(ctr0 + i, key);
+}
+
+void oracle_fill_f32(uint64_t key, uint64_t ctr0, uint64_t n, float *out)
+{
+    for (uint64_t i = 0; i < n; ++i)
+        out[i] = oracle_to_f32(oracle_squares32(ctr0 + i, key));
+}
+
+void oracle_fill_f64(uint64_t key, uint64_t ctr0, uint64_t n, double *out)
+{
+    for (uint64_t i = 0; i < n; ++i)
+        out[i] = oracle_to_f64(oracle_squares64(ctr0 + i, key));
+}
+
+/* Width in bytes of one output of a kind, 0 for an unknown kind. */
+int oracle_kind_bytes(int kind)
+{
+    switch (kind) {
+    case ORACLE_U32: case ORACLE_F32: return 4;
+    case ORACLE_U64: case ORACLE_F64: return 8;
+    default: return 0;
+    }
+}
+
+/* Fill `n` outputs of `kind` at `dst` (any alignment: bytes are copied). */
+static int fill_kind(int kind, uint64_t key, uint64_t ctr0, uint64_t n,
+                     unsigned char *dst)
+{
+    for (uint64_t i = 0; i < n; ++i) {
+        const uint64_t c = ctr0 + i;
+        switch (kind) {
+        case ORACLE_U32: { uint32_t v = oracle_squares32(c, key); memcpy(dst + 4 * i, &v, 4); break; }
+        case ORACLE_F32: { float v = oracle_to_f32(oracle_squares32(c, key)); memcpy(dst + 4 * i, &v, 4); break; }
+        case ORACLE_U64: { uint64_t v = oracle_squares64(c, key); memcpy(dst + 8 * i, &v, 8); break; }
+        case ORACLE_F64: { double v = oracle_to_f64(oracle_squares64(c, key)); memcpy(dst + 8 * i, &v, 8); break; }
+        default: return -1;
+        }
+    }
+    return 0;
+}
+
+/* Ragged batch: stream s fills lens[s] outputs of kinds[s] from counter
+ * ctr0s[s] under keys[s], written at byte offset offs[s] of `out`.  This is
+ * the paper's "more keys give more streams" (Section 3) laid out as one
+ * output arena.  Returns 0, or -1 on an unknown kind. */
+int oracle_fill_batch(uint32_t m, const uint64_t *keys, const uint64_t *ctr0s,
+                      const uint64_t *lens, const uint64_t *offs,
+                      const uint8_t *kinds, unsigned char *out)
+{
+    for (uint32_t s = 0; s < m; ++s)
+        if (fill_kind(kinds[s], keys[s], ctr0s[s], lens[s], out + offs[s]) != 0)
+            return -1;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Exact sum over a counter range (the fused consumer).  The sum is taken of
+ * the integers whose scaled values are the outputs:
+ *   U32: squares32          F32: squares32 >> 8   (value = sum * 2^-24)
+ *   U64: squares64          F64: squares64 >> 11  (value = sum * 2^-53)
+ * as an exact 128-bit integer, so it does not depend on summation order.
+ * out[0] = low 64 bits, out[1] = high 64 bits.  Returns 0, or -1 on an
+ * unknown kind.
+ * ------------------------------------------------------------------------ */
+int oracle_sum(int kind, uint64_t key, uint64_t ctr0, uint64_t n, uint64_t out[2])
+{
+    unsigned __int128 acc = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+        const uint64_t c = ctr0 + i;
+        switch (kind) {
+        case ORACLE_U32: acc += oracle_squares32(c, key); break;
+        case ORACLE_F32: acc += oracle_squares32(c, key) >> 8; break;
+        case ORACLE_U64: acc += oracle_squares64(c, key); break;
+        case ORACLE_F64: acc += oracle_squares64(c, key) >> 11; break;
+        default: return -1;
+        }
+    }
+    out[0] = (uint64_t)acc;
+    out[1] = (uint64_t)(acc >> 64);
+    return 0;
+}

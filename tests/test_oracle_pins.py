@@ -1,0 +1,341 @@
+"""CPU tests of the oracle against what the paper and the mathematics fix.
+
+The oracle is checked against the pin battery in ``pins.py`` (closed forms,
+hand-worked examples, the squares64/squares32 identity, a balance screen),
+plus bulk properties: counter order and wrap, the Weyl identity the paper
+relies on, the exact uniform conversions and the exact sum.  A mutation
+battery shows that each plausible transcription mistake fails at least one
+pin, so the pins are not vacuous.
+"""
+from __future__ import annotations
+
+import time
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from pins import ALL_PINS, EDGE_WORDS, M64, OracleImpl, balance_screen, load_worked_examples, pin_balance
+
+U64_ = np.uint64
+
+
+# ---------------------------------------------------------------- oracle pins
+@pytest.mark.parametrize("name", sorted(ALL_PINS))
+def test_oracle_passes_pin(oracle_mod, name):
+    impl = OracleImpl(oracle_mod)
+    if name == "balance":
+        bad = pin_balance(impl, n=1 << 24)  # 2^24 outputs, as on the 64 MiB fill
+    else:
+        bad = ALL_PINS[name](impl)
+    assert not bad, bad
+
+
+def test_worked_examples_nontrivial():
+    rows = load_worked_examples()
+    assert len(rows) >= 10
+    assert len({r[1] for r in rows}) >= 4  # several keys
+
+
+# ---------------------------------------------------------------- mutation battery
+def _model(ctr, key, out64, *, swap_args=False, z_plus_one=False, z_minus=False, skip_rot=(),
+           rot_amt=32, shift_not_rot=False, addends="yzyzy", low_out=False, no_cross=False,
+           t_after_rot=False, r5_no_shift=False, xor_to_add=False, y32=False, rounds=4):
+    """Numpy model of the rounds with switches for plausible mistakes.  Only
+    used to show the pins catch each mistake; never a reference for anything."""
+    ctr = ctr.astype(U64_)
+    key = key.astype(U64_)
+    s32, lo = U64_(32), U64_(0xFFFFFFFF)
+    if y32:
+        y = ((ctr & lo) * (key & lo)) & lo
+    else:
+        y = ctr * key
+    if swap_args:
+        z = y + ctr
+    elif z_plus_one:
+        z = y + U64_(1)
+    elif z_minus:
+        z = y - key
+    else:
+        z = y + key
+    add = {"y": y, "z": z}
+
+    def sq(x):
+        return (x & lo) * (x & lo) if no_cross else x * x
+
+    def rot(x):
+        if shift_not_rot:
+            return x >> s32
+        a = U64_(rot_amt)
+        return (x >> a) | (x << (U64_(64) - a))
+
+    x = y
+    for r in range(1, rounds):
+        x = sq(x) + add[addends[r - 1]]
+        if r not in skip_rot:
+            x = rot(x)
+    t = sq(x) + add[addends[rounds - 1]]
+    if not out64:
+        return (t & lo) if low_out else (t >> s32)
+    x5 = t if t_after_rot else rot(t)
+    if t_after_rot:
+        t = rot(t)
+    r5 = sq(x5) + add[addends[rounds]]
+    r5 = r5 if r5_no_shift else (r5 >> s32)
+    return (t + r5) if xor_to_add else (t ^ r5)
+
+
+class ModelImpl:
+    def __init__(self, kw32=None, kw64=None):
+        self.kw32 = kw32 or {}
+        self.kw64 = kw64 or {}
+
+    def sq32(self, c, k):
+        return _model(c, k, False, **self.kw32)
+
+    def sq64(self, c, k):
+        return _model(c, k, True, **self.kw64)
+
+    def range32(self, key, ctr0, n):
+        c = (U64_(ctr0) + np.arange(n, dtype=U64_)).astype(U64_)
+        return self.sq32(c, np.full(n, key, dtype=U64_))
+
+    def range64(self, key, ctr0, n):
+        c = (U64_(ctr0) + np.arange(n, dtype=U64_)).astype(U64_)
+        return self.sq64(c, np.full(n, key, dtype=U64_))
+
+
+def _both(**kw):
+    return ModelImpl(kw, kw)
+
+
+MUTANTS = {
+    "ctr_key_roles_swapped": _both(swap_args=True),
+    "z_is_y_plus_1": _both(z_plus_one=True),
+    "z_is_ctr_minus_1_times_key": _both(z_minus=True),
+    "no_rotate_round1": _both(skip_rot=(1,)),
+    "no_rotate_round2": _both(skip_rot=(2,)),
+    "no_rotate_round3": _both(skip_rot=(3,)),
+    "rotate_by_16": _both(rot_amt=16),
+    "rotate_by_31": _both(rot_amt=31),
+    "shift_instead_of_rotate": _both(shift_not_rot=True),
+    "addends_zyzyz": _both(addends="zyzyz"),
+    "addends_all_y": _both(addends="yyyyy"),
+    "addends_yzyyy": _both(addends="yzyyy"),
+    "cross_term_dropped": _both(no_cross=True),
+    "ctr_key_product_32bit": _both(y32=True),
+    "three_rounds": ModelImpl({"rounds": 3}, {"rounds": 3}),
+    "five_rounds_32": ModelImpl({"rounds": 5, "addends": "yzyzyz"}, {}),
+    "sq32_low_half": ModelImpl({"low_out": True}, {}),
+    "sq64_t_after_rotate": ModelImpl({}, {"t_after_rot": True}),
+    "sq64_round5_adds_z": ModelImpl({}, {"addends": "yzyzz"}),
+    "sq64_round5_unshifted": ModelImpl({}, {"r5_no_shift": True}),
+    "sq64_add_not_xor": ModelImpl({}, {"xor_to_add": True}),
+}
+
+
+def test_unmutated_model_passes_all_pins():
+    impl = ModelImpl()
+    for name, pin in ALL_PINS.items():
+        assert not pin(impl), name
+
+
+@pytest.mark.parametrize("mutant", sorted(MUTANTS))
+def test_each_mutant_fails_a_pin(mutant):
+    impl = MUTANTS[mutant]
+    failed = [name for name, pin in ALL_PINS.items() if pin(impl)]
+    assert failed, f"mutant {mutant} passes every pin"
+
+
+# ---------------------------------------------------------------- transcription cross-check
+def _bigint_sq(ctr, key, out64):
+    """Arbitrary-precision re-evaluation.  A second transcription, kept as a
+    consistency check of the C build; not counted as a pin."""
+    y = (ctr * key) % 2**64
+    z = ((ctr + 1) * key) % 2**64
+    x = y
+    for a in (y, z, y):
+        x = (x * x + a) % 2**64
+        x = ((x >> 32) | (x << 32)) % 2**64
+    t = (x * x + z) % 2**64
+    if not out64:
+        return t >> 32
+    x = ((t >> 32) | (t << 32)) % 2**64
+    return t ^ (((x * x + y) % 2**64) >> 32)
+
+
+def test_transcription_bigint_and_trace(oracle_mod):
+    g = np.random.Generator(np.random.PCG64(21))
+    pairs = [(a, b) for a in EDGE_WORDS for b in EDGE_WORDS]
+    pairs += [(int(a), int(b)) for a, b in g.integers(0, 1 << 64, size=(5000, 2), dtype=np.uint64, endpoint=False)]
+    for c, k in pairs:
+        assert oracle_mod.squares32(c, k) == _bigint_sq(c, k, False)
+        assert oracle_mod.squares64(c, k) == _bigint_sq(c, k, True)
+    # the trace's round-4 value is t; its high half is squares32
+    for c, k in pairs[:500]:
+        tr = oracle_mod.trace(c, k)
+        assert tr[3] >> 32 == oracle_mod.squares32(c, k)
+        assert tr[3] ^ (tr[4] >> 32) == oracle_mod.squares64(c, k)
+
+
+# ---------------------------------------------------------------- bulk: counters
+def test_fill_is_counter_order(oracle_mod):
+    o = oracle_mod
+    key, ctr0 = 0xC8E3A1F7D49B2650, 0x123456789ABCDEF0
+    a = o.fill(o.U32, key, ctr0, 300)
+    b = o.fill(o.U64, key, ctr0, 300)
+    for i in range(300):
+        assert int(a[i]) == o.squares32(ctr0 + i, key)
+        assert int(b[i]) == o.squares64(ctr0 + i, key)
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2, 3])
+def test_counter_wrap(oracle_mod, kind):
+    """The counter is a 64-bit integer (Section 3): a range that passes 2^64-1
+    continues at 0 with the same key."""
+    o = oracle_mod
+    key = 0x5F0E9D8C7B6A4132
+    for d in (1, 2, 7, 100):
+        n = 257
+        whole = o.fill(kind, key, 2**64 - d, n)
+        parts = np.concatenate([o.fill(kind, key, 2**64 - d, d), o.fill(kind, key, 0, n - d)])
+        assert whole.tobytes() == parts.tobytes()
+
+
+def test_weyl_identity():
+    """Section 2: repeating w += s i times gives i*s mod 2^64, the identity that
+    lets counter*key stand in for a Weyl sequence (and that a kernel stepping
+    y by key, or by a multiple of key, relies on)."""
+    g = np.random.Generator(np.random.PCG64(22))
+    for s in [int(v) for v in g.integers(0, 1 << 64, size=4, dtype=np.uint64, endpoint=False)] + [M64, 1 << 63]:
+        w = 0
+        for i in range(1 << 16):
+            assert w == (i * s) % 2**64
+            w = (w + s) % 2**64
+    # jumps: y(c0 + j) == y(c0) + j*key for strides used by bulk stepping
+    for key in (0x9E3779B97F4A7C15, M64):
+        for c0 in (0, M64 - 5, 1 << 63):
+            for j in (1, 4, 2, 65536, 1 << 32, (1 << 64) - 3):
+                assert ((c0 + j) * key) % 2**64 == ((c0 * key) + j * key) % 2**64
+    # (ctr+1)*key == ctr*key + key: the second addend of one counter is the
+    # first addend of the next
+    for c in EDGE_WORDS:
+        assert ((c + 1) * 0x6A09E667F3BCC909) % 2**64 == (c * 0x6A09E667F3BCC909 + 0x6A09E667F3BCC909) % 2**64
+
+
+def test_threads_equal_single(oracle_mod):
+    o = oracle_mod
+    key, ctr0 = 0xA3B1C2D4E5F60789, 2**64 - 5000
+    for kind in (0, 1, 2, 3):
+        a = o.fill(kind, key, ctr0, 100003, threads=1)
+        b = o.fill(kind, key, ctr0, 100003, threads=7)
+        assert a.tobytes() == b.tobytes()
+
+
+# ---------------------------------------------------------------- uniform conversions
+def test_uniform_f32_is_top_24_bits(oracle_mod):
+    """f32 = top 24 bits of the 32-bit output scaled into [0,1): an integer
+    multiple of 2^-24 with 0 <= u*2^-32 - f < 2^-24."""
+    o = oracle_mod
+    key, ctr0, n = 0x2B7E151628AED2A6, 99, 1 << 16
+    u = o.fill(o.U32, key, ctr0, n).astype(np.int64)
+    f = o.fill(o.F32, key, ctr0, n)
+    m = f.astype(np.float64) * 2.0**24
+    assert np.all(m == np.floor(m))
+    d = u.astype(np.float64) * 2.0**-32 - f.astype(np.float64)
+    assert np.all(d >= 0) and np.all(d < 2.0**-24)
+    assert np.all(f >= 0) and np.all(f < 1)
+    lib = o.lib()
+    assert lib.oracle_to_f32(0) == 0.0
+    assert lib.oracle_to_f32(0xFFFFFFFF) == 1.0 - 2.0**-24
+    assert lib.oracle_to_f32(0x80000000) == 0.5
+    assert lib.oracle_to_f32(0xFF) == 0.0 and lib.oracle_to_f32(0x100) == 2.0**-24
+
+
+def test_uniform_f64_is_top_53_bits(oracle_mod):
+    """f64 = top 53 bits of the 64-bit output scaled into [0,1), exactly."""
+    o = oracle_mod
+    key, ctr0, n = 0x2B7E151628AED2A6, 2**64 - 1000, 1 << 14
+    u = o.fill(o.U64, key, ctr0, n)
+    f = o.fill(o.F64, key, ctr0, n)
+    for i in range(0, n, 7):
+        exact = Fraction(int(u[i]), 2**64)
+        fi = Fraction(float(f[i]))
+        assert (fi * 2**53).denominator == 1
+        assert 0 <= exact - fi < Fraction(1, 2**53)
+    lib = o.lib()
+    assert lib.oracle_to_f64(0) == 0.0
+    assert lib.oracle_to_f64(M64) == 1.0 - 2.0**-53
+    assert lib.oracle_to_f64(1 << 63) == 0.5
+    assert lib.oracle_to_f64(2047) == 0.0 and lib.oracle_to_f64(2048) == 2.0**-53
+
+
+# ---------------------------------------------------------------- exact sum
+@pytest.mark.parametrize("kind", [0, 1, 2, 3])
+def test_exact_sum(oracle_mod, kind):
+    o = oracle_mod
+    key, ctr0 = 0x3C6EF372FE94F82B, 2**64 - 12345
+    n = 1 << 17
+    vals = o.fill({0: o.U32, 1: o.U32, 2: o.U64, 3: o.U64}[kind], key, ctr0, n)
+    shift = {0: 0, 1: 8, 2: 0, 3: 11}[kind]
+    expect = sum(int(v) >> shift for v in vals)
+    assert o.exact_sum(kind, key, ctr0, n) == expect
+    assert o.exact_sum(kind, key, ctr0, n, threads=5) == expect
+    # additivity over a split point, including across the wrap
+    for b in (0, 1, 12345, 77777, n):
+        left = o.exact_sum(kind, key, ctr0, b)
+        right = o.exact_sum(kind, key, (ctr0 + b) % 2**64, n - b)
+        assert left + right == expect
+    # the scaled value of a uniform kind equals the float sum done exactly
+    if kind in (1, 3):
+        fv = o.fill(kind, key, ctr0, 4096)
+        exact = sum(Fraction(float(v)) for v in fv)
+        assert Fraction(o.exact_sum(kind, key, ctr0, 4096)) * Fraction(2) ** o.KIND_SUM_SCALE[kind] == exact
+    assert o.exact_sum(kind, key, ctr0, 0) == 0
+
+
+def test_rounded_value_is_nearest_even(oracle_mod):
+    o = oracle_mod
+    # ties to even on a 54-bit integer
+    assert o.rounded_value(o.U64, 2**53 + 1) == float(2**53)
+    assert o.rounded_value(o.U64, 2**53 + 3) == float(2**53 + 4)
+    big = (1 << 127) + (1 << 74) + 1  # just above a tie: rounds up
+    assert o.rounded_value(o.U64, big) == float((1 << 127) + (1 << 75))
+    assert o.rounded_value(o.F64, 2**53) == 1.0
+
+
+def test_sum_near_u128_limit(oracle_mod):
+    """The 128-bit accumulator carries: a sum of 2^20 values near 2^64 exceeds
+    2^64 and must keep its high word."""
+    o = oracle_mod
+    s = o.exact_sum(o.U64, 0x8F1BBCDCCA62C1D6, 7, 1 << 20)
+    assert s > 2**64 and s < (1 << 20) * 2**64
+
+
+# ---------------------------------------------------------------- batch
+def test_batch_matches_per_stream(oracle_mod):
+    from paper_2004_06278_amd import workloads as W
+
+    o = oracle_mod
+    b = W.small_random_batch(seed=31, m=60, max_len=700)
+    arena = o.fill_batch(b.keys, b.ctr0s, b.lens, b.offs, b.kinds, b.arena_bytes)
+    for s in range(b.m):
+        k, L, off = int(b.kinds[s]), int(b.lens[s]), int(b.offs[s])
+        ref = o.fill(k, int(b.keys[s]), int(b.ctr0s[s]), L).view(np.uint8)
+        assert arena[off: off + ref.size].tobytes() == ref.tobytes()
+
+
+def test_config1_oracle_under_one_second(oracle_mod):
+    """The 2^24-output squares32 fill runs on one core in well under a second."""
+    o = oracle_mod
+    from paper_2004_06278_amd import workloads as W
+
+    c = W.plain_fill_case()
+    u = np.ones(c.n, dtype=np.uint32)  # pages touched before timing
+    dt = []
+    for _ in range(2):
+        t0 = time.perf_counter()
+        o.fill_into(o.U32, c.key, c.ctr0, u)
+        dt.append(time.perf_counter() - t0)
+    assert min(dt) < 1.0, dt
+    assert not balance_screen(u, 32)
