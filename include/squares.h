@@ -1,0 +1,252 @@
+/*
+ * squares.h -- C ABI of libsquares.so, the MI355X (gfx950) implementation of
+ * the Squares counter-based RNG (B. Widynski, "Squares: A Fast Counter-Based
+ * RNG", arXiv 2004.06278).
+ *
+ * The generators are pure functions of a 64-bit counter and a 64-bit key:
+ *   squares32(ctr, key) -> uint32, four rounds          (Section 2)
+ *   squares64(ctr, key) -> uint64, five rounds          (Section 5)
+ * Each round squares the 64-bit state modulo 2^64, adds ctr*key or
+ * (ctr+1)*key (the Weyl terms, Sections 2 and 3) and swaps the two 32-bit
+ * halves (Section 3).  The library evaluates them over counter ranges on the
+ * GPU; every entry point below launches hand-written HIP kernels and does no
+ * generator arithmetic on the host.
+ *
+ * Conventions shared by every call:
+ *  - Pointers named out/ws/keys/... are DEVICE pointers (hipMalloc'd or
+ *    torch CUDA tensors) unless stated; the caller owns them and must keep
+ *    them valid until the stream work completes.  Nothing on the fill,
+ *    reduce and batch paths allocates device memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Calls are asynchronous on that stream; a device fault surfaces at the
+ *    next synchronisation, as with any HIP call.
+ *  - Counters run ctr0, ctr0+1, ... modulo 2^64: a range that passes
+ *    2^64-1 continues at 0 with the same key (the counter is a 64-bit
+ *    integer, Section 3).  No error is raised on wrap.
+ *  - Any key is accepted, including 0 and even keys; choosing keys with
+ *    irregular bit patterns (Section 3) is the caller's concern.
+ *  - The argument order of the bulk calls is (key, ctr0); the paper's scalar
+ *    functions take (ctr, key).  out[i] == squaresNN(ctr0 + i, key).
+ *  - Every call returns an sq_status; sq_last_error() gives a message for
+ *    the calling thread's last non-OK status.  No C++ exception crosses the
+ *    ABI.
+ */
+#ifndef SQUARES_H
+#define SQUARES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Output kinds.  U32/F32 come from squares32, U64/F64 from squares64.
+ * F32 = (squares32 >> 8) * 2^-24 and F64 = (squares64 >> 11) * 2^-53: the
+ * paper reports 32-bit and 53-bit precision floating point outputs
+ * (Section 5) without a formula; these take the top 24 / 53 bits, which
+ * converts exactly into [0, 1). */
+typedef enum { SQ_U32 = 0, SQ_F32 = 1, SQ_U64 = 2, SQ_F64 = 3 } sq_kind;
+
+typedef enum {
+    SQ_OK = 0,
+    SQ_EINVAL = -1,    /* bad argument (null pointer with n > 0, unknown kind, ...) */
+    SQ_EALIGN = -2,    /* pointer or byte offset not a multiple of the element size */
+    SQ_ENOMEM = -3,    /* workspace too small, or a request larger than a budget */
+    SQ_EHIP = -4,      /* a HIP runtime call failed (message in sq_last_error) */
+    SQ_EBUSY = -5,     /* resource in use (e.g. request not finished yet) */
+    SQ_ENOTFOUND = -6  /* unknown request id / plan */
+} sq_status;
+
+/* Message for the calling thread's most recent non-OK status ("" if none). */
+const char *sq_last_error(void);
+
+/* Library version (major*10000 + minor*100 + patch). */
+int sq_version(void);
+
+/* Binds the current HIP device, reads its CU count and loads the tuning
+ * table from $SQ_TUNE_CACHE if set.  Called implicitly by every entry point;
+ * calling it first keeps that work out of a timed region. */
+int sq_init(void);
+
+/* ------------------------------------------------------------------------
+ * Bulk fills over a counter range (Section 2 squares32, Section 5 squares64).
+ *   out[i] = f(ctr0 + i mod 2^64, key),  i in [0, n)
+ * `out` must be aligned to the element size (4 or 8 bytes), else SQ_EALIGN;
+ * 16-byte alignment is not required (a misaligned head and tail are
+ * written element by element).  n == 0 returns SQ_OK without a launch; a
+ * null `out` with n > 0 is SQ_EINVAL.  out must hold n elements.
+ * ------------------------------------------------------------------------ */
+int sq32_fill(uint64_t key, uint64_t ctr0, uint64_t n, uint32_t *out, void *stream);
+int sq64_fill(uint64_t key, uint64_t ctr0, uint64_t n, uint64_t *out, void *stream);
+/* Uniform fills: the conversion is fused into the generating kernel. */
+int sq_uniform_f32(uint64_t key, uint64_t ctr0, uint64_t n, float *out, void *stream);
+int sq_uniform_f64(uint64_t key, uint64_t ctr0, uint64_t n, double *out, void *stream);
+/* The four fills above behind one kind argument. */
+int sq_fill(sq_kind kind, uint64_t key, uint64_t ctr0, uint64_t n, void *out, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Launch configurations (chosen by the autotuner; explicit for tests).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    uint32_t block;        /* threads per workgroup: 256, 512 or 1024 */
+    uint32_t unroll;       /* 16-byte vectors per lane per step: 4 or 8 (fill);
+                              outputs per lane per step for reduce: 1, 2 or 4 */
+    uint32_t grid_per_cu;  /* workgroups per compute unit (grid = CUs * this), 1..64 */
+    uint32_t xcd_map;      /* 0: consecutive chunks round-robin over the 8 XCDs;
+                              1: each XCD takes one contiguous eighth of the range */
+    uint32_t tile_log2;    /* batch only: outputs per tile = 2^tile_log2, 12..24 */
+} sq_launch_cfg;
+
+/* Operation classes the tuning table is keyed by. */
+typedef enum { SQ_OP_FILL = 0, SQ_OP_REDUCE = 1, SQ_OP_BATCH = 2 } sq_op;
+
+/* Same as sq_fill with an explicit launch configuration (SQ_EINVAL if the
+ * configuration is outside the documented ranges). */
+int sq_fill_cfg(sq_kind kind, uint64_t key, uint64_t ctr0, uint64_t n, void *out,
+                const sq_launch_cfg *cfg, void *stream);
+
+/* Tuning table: one configuration per (op, kind, size bucket), size buckets
+ * by n (outputs; for SQ_OP_BATCH the mean stream length):
+ * [0,2^16), [2^16,2^20), [2^20,2^24), [2^24,2^28), [2^28,inf). */
+int sq_tune_get(sq_op op, sq_kind kind, uint64_t n, sq_launch_cfg *cfg);
+int sq_tune_set(sq_op op, sq_kind kind, uint64_t n, const sq_launch_cfg *cfg);
+/* Load / save the table as JSON text (host file paths). */
+int sq_tune_load(const char *path);
+int sq_tune_save(const char *path);
+/* Autotuner: for every op/kind it times the candidate configurations on
+ * scratch buffers of up to `max_bytes` bytes that it allocates itself (this
+ * call is not on the hot path), keeps only candidates whose output is
+ * bit-identical to the default configuration's, and stores the fastest in
+ * the table.  op_mask bit i selects sq_op i.  Writes the table to
+ * `save_path` when non-null.  Synchronous. */
+int sq_autotune(uint32_t op_mask, uint64_t max_bytes, const char *save_path);
+
+/* ------------------------------------------------------------------------
+ * Fused consumer: exact sum over a counter range with no per-element writes.
+ * The sum is of the integers whose scaled values are the outputs:
+ *   SQ_U32: squares32        SQ_F32: squares32 >> 8   (value = sum * 2^-24)
+ *   SQ_U64: squares64        SQ_F64: squares64 >> 11  (value = sum * 2^-53)
+ * as an exact 128-bit integer, so the result does not depend on the order of
+ * summation or on the launch configuration.  `value` is that sum times the
+ * kind's scale rounded to the nearest double (ties to even).
+ * `out` is a DEVICE pointer to one sq_sum_result.  `ws` is a device
+ * workspace of at least sq_reduce_workspace_bytes(n) bytes (16-byte
+ * aligned), else SQ_ENOMEM.  n == 0 writes a zero result.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    uint64_t lo;     /* low 64 bits of the exact integer sum */
+    uint64_t hi;     /* high 64 bits */
+    double value;    /* sum * 2^scale rounded to nearest even */
+    uint64_t n;      /* number of outputs summed */
+} sq_sum_result;
+
+size_t sq_reduce_workspace_bytes(uint64_t n);
+int sq_reduce(sq_kind kind, uint64_t key, uint64_t ctr0, uint64_t n, sq_sum_result *out,
+              void *ws, size_t ws_bytes, void *stream);
+int sq_reduce_cfg(sq_kind kind, uint64_t key, uint64_t ctr0, uint64_t n, sq_sum_result *out,
+                  void *ws, size_t ws_bytes, const sq_launch_cfg *cfg, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Ragged batch: m streams in one launch (more keys give more streams,
+ * Section 3).  Stream s writes lens[s] outputs of kind kinds[s] from counter
+ * ctr0s[s] under keys[s] at byte offset offs[s] of the arena `out` of
+ * `out_bytes` bytes.  All five descriptor arrays are DEVICE arrays of m
+ * entries; offs[s] must be a multiple of the element size, streams must not
+ * overlap.  The kernels check every descriptor on the device: a stream with
+ * an unknown kind, a misaligned offset or a range past out_bytes is skipped
+ * (nothing written) and counted; sq_batch_errors() reads that count.
+ * `ws` needs sq_batch_workspace_bytes(m) bytes (16-byte aligned).
+ * The work is split into tiles of 2^tile_log2 outputs; a tile scan and one
+ * persistent kernel run on `stream`.
+ * ------------------------------------------------------------------------ */
+size_t sq_batch_workspace_bytes(uint32_t m);
+int sq_fill_batch(const uint64_t *keys, const uint64_t *ctr0s, const uint64_t *lens,
+                  const uint64_t *offs, const uint8_t *kinds, uint32_t m, void *out,
+                  uint64_t out_bytes, void *ws, size_t ws_bytes, void *stream);
+int sq_fill_batch_cfg(const uint64_t *keys, const uint64_t *ctr0s, const uint64_t *lens,
+                      const uint64_t *offs, const uint8_t *kinds, uint32_t m, void *out,
+                      uint64_t out_bytes, void *ws, size_t ws_bytes, const sq_launch_cfg *cfg,
+                      void *stream);
+/* Number of skipped streams of the last batch that used `ws` (synchronises
+ * `stream`). */
+int sq_batch_errors(const void *ws, void *stream, uint32_t *count);
+
+/* Batch plan: the tile scan and the persistent kernel captured once into a
+ * HIP graph over fixed descriptor, arena and workspace addresses.  Each
+ * launch replays the graph and reads the descriptor arrays' CURRENT
+ * contents, so the caller may rewrite keys/ctr0s/lens/offs/kinds (same m)
+ * between launches without re-capture. */
+typedef struct sq_batch_plan sq_batch_plan;
+int sq_batch_plan_create(const uint64_t *keys, const uint64_t *ctr0s, const uint64_t *lens,
+                         const uint64_t *offs, const uint8_t *kinds, uint32_t m, void *out,
+                         uint64_t out_bytes, void *ws, size_t ws_bytes,
+                         const sq_launch_cfg *cfg /* NULL = tuned */, sq_batch_plan **plan);
+int sq_batch_plan_launch(sq_batch_plan *plan, void *stream);
+int sq_batch_plan_destroy(sq_batch_plan *plan);
+
+/* ------------------------------------------------------------------------
+ * Serving: a continuous-batching request loop.  The generator is stateless
+ * (Section 1, Section 6), so a request's whole state is (key, next counter,
+ * outputs left); the server keeps it in a device slot table.
+ *  - submit() queues a request; a scheduler thread admits queued requests
+ *    in arrival order while free slots and HBM budget allow (the request's
+ *    output is carved from a device arena of hbm_budget_bytes owned by the
+ *    server), so requests are admitted while others are running.
+ *  - Each tick is one launch of the batch kernel over the next chunk (at
+ *    most chunk_cap outputs) of every admitted, unfinished request; up to
+ *    n_streams ticks run concurrently on separate streams.
+ *  - A request's outputs are identical to sq_fill(kind, key, ctr0, n) no
+ *    matter what else runs with it.
+ *  - Latency = completion seen by the scheduler minus submit() time.
+ * ------------------------------------------------------------------------ */
+typedef struct sq_server sq_server;
+
+typedef struct {
+    uint64_t hbm_budget_bytes;  /* output arena size (bytes); every admitted request's
+                                   output lives here until released */
+    uint32_t max_slots;         /* admitted-but-unreleased requests, 1..65536 */
+    uint64_t chunk_cap;         /* outputs of one request per tick (>= 4096) */
+    uint32_t n_streams;         /* concurrent ticks, 1..8 */
+    uint32_t tile_log2;         /* tile of the tick kernel (0 = tuned) */
+} sq_server_cfg;
+
+/* submit() flags */
+#define SQ_SERVE_DISCARD 1u     /* free the output as soon as the request completes */
+
+typedef struct {
+    uint64_t submitted, admitted, completed, released;
+    uint64_t outputs, bytes;    /* totals over completed requests */
+    uint64_t ticks;
+    uint64_t queued_now, active_now, arena_used_bytes;
+    double p50_s, p90_s, p99_s, max_s, mean_s;  /* latency over completed requests */
+    double first_submit_s, last_complete_s;     /* on the server's steady clock */
+} sq_server_stats_t;
+
+int sq_server_create(const sq_server_cfg *cfg, sq_server **srv);
+/* SQ_ENOMEM if the request's bytes exceed hbm_budget_bytes (it could never
+ * be admitted); SQ_EINVAL for an unknown kind or n == 0. */
+int sq_server_submit(sq_server *srv, sq_kind kind, uint64_t key, uint64_t ctr0, uint64_t n,
+                     uint32_t flags, uint64_t *req_id);
+/* *done = 1 once every output of the request is written. */
+int sq_server_poll(sq_server *srv, uint64_t req_id, int *done);
+/* Blocks until the request completes. */
+int sq_server_wait(sq_server *srv, uint64_t req_id);
+/* Device address and size of a completed request's output (SQ_EBUSY if not
+ * complete; SQ_ENOTFOUND if released or discarded). */
+int sq_server_result(sq_server *srv, uint64_t req_id, void **dev_ptr, uint64_t *bytes);
+/* Latency of a completed request in seconds. */
+int sq_server_latency(sq_server *srv, uint64_t req_id, double *seconds);
+/* Returns a completed request's output space to the arena. */
+int sq_server_release(sq_server *srv, uint64_t req_id);
+/* Cancels a request that is still queued (SQ_EBUSY once admitted). */
+int sq_server_cancel(sq_server *srv, uint64_t req_id);
+int sq_server_stats(sq_server *srv, sq_server_stats_t *out);
+/* Drains admitted work, then frees the server and its arena. */
+int sq_server_destroy(sq_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SQUARES_H */

@@ -1,0 +1,262 @@
+// C ABI of libsquares.so: argument checks, launch-configuration lookup and
+// kernel launches for the fill, reduce and batch entry points declared in
+// include/squares.h.  No generator arithmetic happens on the host.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+
+#include "sq_internal.hpp"
+
+namespace sqi {
+
+static thread_local std::string g_err;
+
+int fail(int status, const std::string& msg) {
+  g_err = msg;
+  return status;
+}
+
+int fail_hip(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return SQ_EHIP;
+}
+
+static std::mutex g_dev_mu;
+static std::unordered_map<int, DeviceInfo> g_devs;
+static thread_local DeviceInfo t_cur;
+int tune_autoload();  // sq_tune.cpp
+
+int ensure_init() {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+  if (t_cur.device == dev) return SQ_OK;
+  {
+    std::lock_guard<std::mutex> g(g_dev_mu);
+    auto it = g_devs.find(dev);
+    if (it == g_devs.end()) {
+      DeviceInfo di;
+      di.device = dev;
+      int cus = 0;
+      e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+      if (e != hipSuccess) return fail_hip(e, "hipDeviceGetAttribute(CU count)");
+      di.cus = cus > 0 ? cus : 256;
+      it = g_devs.emplace(dev, di).first;
+    }
+    t_cur = it->second;
+  }
+  return tune_autoload();
+}
+
+const DeviceInfo& device_info() { return t_cur; }
+
+}  // namespace sqi
+
+using namespace sqi;
+
+#define SQ_INIT_OR_RETURN()          \
+  do {                               \
+    int rc_ = ensure_init();         \
+    if (rc_ != SQ_OK) return rc_;    \
+  } while (0)
+
+extern "C" {
+
+const char* sq_last_error(void) { return g_err.c_str(); }
+
+int sq_version(void) { return 10000; }
+
+int sq_init(void) {
+  SQ_INIT_OR_RETURN();
+  return SQ_OK;
+}
+
+// ---------------------------------------------------------------- fills
+static int check_fill(int kind, uint64_t n, const void* out) {
+  const int W = kind_bytes(kind);
+  if (W == 0) return fail(SQ_EINVAL, "unknown kind " + std::to_string(kind));
+  if (n == 0) return SQ_OK;
+  if (out == nullptr) return fail(SQ_EINVAL, "null output pointer with n > 0");
+  if (((uintptr_t)out & (uintptr_t)(W - 1)) != 0)
+    return fail(SQ_EALIGN, "output pointer not aligned to " + std::to_string(W) + " bytes");
+  return SQ_OK;
+}
+
+int sq_fill_cfg(sq_kind kind, uint64_t key, uint64_t ctr0, uint64_t n, void* out, const sq_launch_cfg* cfg,
+                void* stream) {
+  int rc = check_fill(kind, n, out);
+  if (rc != SQ_OK || n == 0) return rc;
+  if (cfg == nullptr || !cfg_valid(SQ_OP_FILL, *cfg)) return fail(SQ_EINVAL, "invalid fill launch configuration");
+  SQ_INIT_OR_RETURN();
+  hipError_t e = launch_fill(kind, key, ctr0, n, out, *cfg, (hipStream_t)stream);
+  return e == hipSuccess ? SQ_OK : fail_hip(e, "fill launch");
+}
+
+int sq_fill(sq_kind kind, uint64_t key, uint64_t ctr0, uint64_t n, void* out, void* stream) {
+  int rc = check_fill(kind, n, out);
+  if (rc != SQ_OK || n == 0) return rc;
+  SQ_INIT_OR_RETURN();
+  const sq_launch_cfg cfg = tuned_cfg(SQ_OP_FILL, kind, n);
+  hipError_t e = launch_fill(kind, key, ctr0, n, out, cfg, (hipStream_t)stream);
+  return e == hipSuccess ? SQ_OK : fail_hip(e, "fill launch");
+}
+
+int sq32_fill(uint64_t key, uint64_t ctr0, uint64_t n, uint32_t* out, void* stream) {
+  return sq_fill(SQ_U32, key, ctr0, n, out, stream);
+}
+int sq64_fill(uint64_t key, uint64_t ctr0, uint64_t n, uint64_t* out, void* stream) {
+  return sq_fill(SQ_U64, key, ctr0, n, out, stream);
+}
+int sq_uniform_f32(uint64_t key, uint64_t ctr0, uint64_t n, float* out, void* stream) {
+  return sq_fill(SQ_F32, key, ctr0, n, out, stream);
+}
+int sq_uniform_f64(uint64_t key, uint64_t ctr0, uint64_t n, double* out, void* stream) {
+  return sq_fill(SQ_F64, key, ctr0, n, out, stream);
+}
+
+// ---------------------------------------------------------------- reduce
+size_t sq_reduce_workspace_bytes(uint64_t n) {
+  (void)n;
+  return 16ull * kReduceMaxParts;
+}
+
+int sq_reduce_cfg(sq_kind kind, uint64_t key, uint64_t ctr0, uint64_t n, sq_sum_result* out, void* ws,
+                  size_t ws_bytes, const sq_launch_cfg* cfg, void* stream) {
+  if (kind_bytes(kind) == 0) return fail(SQ_EINVAL, "unknown kind " + std::to_string((int)kind));
+  if (out == nullptr || ws == nullptr) return fail(SQ_EINVAL, "null result or workspace pointer");
+  if (((uintptr_t)out & 7) != 0 || ((uintptr_t)ws & 15) != 0)
+    return fail(SQ_EALIGN, "result must be 8-byte and workspace 16-byte aligned");
+  if (ws_bytes < sq_reduce_workspace_bytes(n))
+    return fail(SQ_ENOMEM, "reduce workspace smaller than sq_reduce_workspace_bytes()");
+  if (cfg == nullptr || !cfg_valid(SQ_OP_REDUCE, *cfg)) return fail(SQ_EINVAL, "invalid reduce launch configuration");
+  SQ_INIT_OR_RETURN();
+  hipError_t e = launch_reduce(kind, key, ctr0, n, out, ws, *cfg, (hipStream_t)stream);
+  return e == hipSuccess ? SQ_OK : fail_hip(e, "reduce launch");
+}
+
+int sq_reduce(sq_kind kind, uint64_t key, uint64_t ctr0, uint64_t n, sq_sum_result* out, void* ws, size_t ws_bytes,
+              void* stream) {
+  if (kind_bytes(kind) == 0) return fail(SQ_EINVAL, "unknown kind " + std::to_string((int)kind));
+  SQ_INIT_OR_RETURN();
+  const sq_launch_cfg cfg = tuned_cfg(SQ_OP_REDUCE, kind, n);
+  return sq_reduce_cfg(kind, key, ctr0, n, out, ws, ws_bytes, &cfg, stream);
+}
+
+// ---------------------------------------------------------------- batch
+size_t sq_batch_workspace_bytes(uint32_t m) { return batch_ws_bytes(m); }
+
+static int check_batch(const uint64_t* keys, const uint64_t* ctr0s, const uint64_t* lens, const uint64_t* offs,
+                       const uint8_t* kinds, uint32_t m, void* out, void* ws, size_t ws_bytes) {
+  if (m == 0) return SQ_OK;
+  if (!keys || !ctr0s || !lens || !offs || !kinds || !out || !ws)
+    return fail(SQ_EINVAL, "null descriptor, output or workspace pointer");
+  if (((uintptr_t)keys | (uintptr_t)ctr0s | (uintptr_t)lens | (uintptr_t)offs) & 7)
+    return fail(SQ_EALIGN, "descriptor arrays must be 8-byte aligned");
+  if (((uintptr_t)out & 7) != 0 || ((uintptr_t)ws & 15) != 0)
+    return fail(SQ_EALIGN, "arena must be 8-byte and workspace 16-byte aligned");
+  if (ws_bytes < batch_ws_bytes(m)) return fail(SQ_ENOMEM, "batch workspace smaller than sq_batch_workspace_bytes()");
+  return SQ_OK;
+}
+
+static uint64_t mean_bucket_len(uint32_t m) {
+  (void)m;
+  return 1ull << 20;  // descriptors are on the device; tune by a typical stream length
+}
+
+int sq_fill_batch_cfg(const uint64_t* keys, const uint64_t* ctr0s, const uint64_t* lens, const uint64_t* offs,
+                      const uint8_t* kinds, uint32_t m, void* out, uint64_t out_bytes, void* ws, size_t ws_bytes,
+                      const sq_launch_cfg* cfg, void* stream) {
+  int rc = check_batch(keys, ctr0s, lens, offs, kinds, m, out, ws, ws_bytes);
+  if (rc != SQ_OK || m == 0) return rc;
+  if (cfg == nullptr || !cfg_valid(SQ_OP_BATCH, *cfg)) return fail(SQ_EINVAL, "invalid batch launch configuration");
+  SQ_INIT_OR_RETURN();
+  BatchDesc d{keys, ctr0s, lens, offs, kinds, m, (unsigned char*)out, out_bytes};
+  hipError_t e = launch_batch(d, ws, *cfg, (hipStream_t)stream);
+  return e == hipSuccess ? SQ_OK : fail_hip(e, "batch launch");
+}
+
+int sq_fill_batch(const uint64_t* keys, const uint64_t* ctr0s, const uint64_t* lens, const uint64_t* offs,
+                  const uint8_t* kinds, uint32_t m, void* out, uint64_t out_bytes, void* ws, size_t ws_bytes,
+                  void* stream) {
+  SQ_INIT_OR_RETURN();
+  const sq_launch_cfg cfg = tuned_cfg(SQ_OP_BATCH, SQ_U32, mean_bucket_len(m));
+  return sq_fill_batch_cfg(keys, ctr0s, lens, offs, kinds, m, out, out_bytes, ws, ws_bytes, &cfg, stream);
+}
+
+int sq_batch_errors(const void* ws, void* stream, uint32_t* count) {
+  if (ws == nullptr || count == nullptr) return fail(SQ_EINVAL, "null workspace or count pointer");
+  SQ_INIT_OR_RETURN();
+  const BatchHdr* h = (const BatchHdr*)ws;
+  uint32_t v = 0;
+  hipError_t e = hipMemcpyAsync(&v, &h->errors, sizeof v, hipMemcpyDeviceToHost, (hipStream_t)stream);
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return fail_hip(e, "reading batch error count");
+  *count = v;
+  return SQ_OK;
+}
+
+// ---------------------------------------------------------------- batch plan (HIP graph)
+struct sq_batch_plan {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int device = -1;
+};
+
+int sq_batch_plan_create(const uint64_t* keys, const uint64_t* ctr0s, const uint64_t* lens, const uint64_t* offs,
+                         const uint8_t* kinds, uint32_t m, void* out, uint64_t out_bytes, void* ws, size_t ws_bytes,
+                         const sq_launch_cfg* cfg, sq_batch_plan** plan) {
+  if (plan == nullptr) return fail(SQ_EINVAL, "null plan pointer");
+  *plan = nullptr;
+  if (m == 0) return fail(SQ_EINVAL, "a plan needs m > 0");
+  int rc = check_batch(keys, ctr0s, lens, offs, kinds, m, out, ws, ws_bytes);
+  if (rc != SQ_OK) return rc;
+  SQ_INIT_OR_RETURN();
+  const sq_launch_cfg c = cfg ? *cfg : tuned_cfg(SQ_OP_BATCH, SQ_U32, mean_bucket_len(m));
+  if (!cfg_valid(SQ_OP_BATCH, c)) return fail(SQ_EINVAL, "invalid batch launch configuration");
+  hipStream_t cap = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+  if (e != hipSuccess) return fail_hip(e, "hipStreamCreate for capture");
+  sq_batch_plan* p = new sq_batch_plan();
+  p->device = device_info().device;
+  BatchDesc d{keys, ctr0s, lens, offs, kinds, m, (unsigned char*)out, out_bytes};
+  e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipError_t le = launch_batch(d, ws, c, cap);
+    hipError_t ee = hipStreamEndCapture(cap, &p->graph);
+    e = le != hipSuccess ? le : ee;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+  hipError_t de = hipStreamDestroy(cap);
+  if (e == hipSuccess) e = de;
+  if (e != hipSuccess) {
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    delete p;
+    return fail_hip(e, "capturing the batch graph");
+  }
+  *plan = p;
+  return SQ_OK;
+}
+
+int sq_batch_plan_launch(sq_batch_plan* plan, void* stream) {
+  if (plan == nullptr || plan->exec == nullptr) return fail(SQ_ENOTFOUND, "null or destroyed plan");
+  hipError_t e = hipGraphLaunch(plan->exec, (hipStream_t)stream);
+  return e == hipSuccess ? SQ_OK : fail_hip(e, "hipGraphLaunch");
+}
+
+int sq_batch_plan_destroy(sq_batch_plan* plan) {
+  if (plan == nullptr) return SQ_OK;
+  hipError_t e1 = plan->exec ? hipGraphExecDestroy(plan->exec) : hipSuccess;
+  hipError_t e2 = plan->graph ? hipGraphDestroy(plan->graph) : hipSuccess;
+  delete plan;
+  if (e1 != hipSuccess) return fail_hip(e1, "hipGraphExecDestroy");
+  if (e2 != hipSuccess) return fail_hip(e2, "hipGraphDestroy");
+  return SQ_OK;
+}
+
+}  // extern "C"

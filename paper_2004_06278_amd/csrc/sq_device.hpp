@@ -1,0 +1,132 @@
+// Device primitives of the Squares generators for gfx950.
+//
+// A round of either generator (Section 2 for squares32, Section 5 for
+// squares64) is
+//     x <- x*x + a (mod 2^64);  x <- x rotated by 32 bits
+// with a the first Weyl term y = ctr*key in odd rounds and the second one
+// z = (ctr+1)*key in even rounds.  On CDNA the 64-bit state lives in two
+// 32-bit VGPRs (xl, xh) and
+//     x*x mod 2^64 = xl*xl + ((2*xl*xh) mod 2^32) * 2^32,
+// so a round is one v_mad_u64_u32 (xl*xl + a, full 64-bit result), one
+// v_mul_lo_u32 (xl*xh) and one v_lshl_add_u32 (the doubled cross term added
+// into the high word).  The rotation is free: it only swaps which register
+// is called "low".  No MFMA: nothing here is a contraction.
+//
+// Consecutive counters share Weyl terms: z(c) = y(c+1), and y advances by
+// key per counter (Section 2: ctr*key replaces the sequence w += s), so a
+// lane that owns counters c..c+E-1 needs E+1 values y(c)..y(c+E), each one
+// 64-bit add from the previous.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sqd {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// rot32(x*x + a)
+__device__ __forceinline__ uint64_t round_rot(uint64_t x, uint64_t a) {
+  const uint32_t xl = (uint32_t)x, xh = (uint32_t)(x >> 32);
+  const uint64_t m = (uint64_t)xl * xl + a;                       // v_mad_u64_u32
+  const uint32_t hi = (uint32_t)(m >> 32) + ((xl * xh) << 1);     // v_mul_lo_u32, v_lshl_add_u32
+  return ((uint64_t)(uint32_t)m << 32) | hi;                      // halves swapped
+}
+
+// x*x + a without the rotation, as (lo, hi) words
+__device__ __forceinline__ void round_norot(uint64_t x, uint64_t a, uint32_t& lo, uint32_t& hi) {
+  const uint32_t xl = (uint32_t)x, xh = (uint32_t)(x >> 32);
+  const uint64_t m = (uint64_t)xl * xl + a;
+  lo = (uint32_t)m;
+  hi = (uint32_t)(m >> 32) + ((xl * xh) << 1);
+}
+
+// Upper 32 bits of x*x + a
+__device__ __forceinline__ uint32_t round_hi(uint64_t x, uint64_t a) {
+  const uint32_t xl = (uint32_t)x, xh = (uint32_t)(x >> 32);
+  const uint64_t m = (uint64_t)xl * xl + a;
+  return (uint32_t)(m >> 32) + ((xl * xh) << 1);
+}
+
+// squares32 from its Weyl terms y = ctr*key, z = (ctr+1)*key.
+__device__ __forceinline__ uint32_t sq32(uint64_t y, uint64_t z) {
+  uint64_t x = round_rot(y, y);  // round 1 (x starts as y)
+  x = round_rot(x, z);           // round 2
+  x = round_rot(x, y);           // round 3
+  return round_hi(x, z);         // round 4: upper half of x*x + z
+}
+
+// squares64: round 4 keeps t = x*x + z whole; round 5 squares rot32(t), adds
+// y and its upper 32 bits are XORed into the low word of t.
+__device__ __forceinline__ uint64_t sq64(uint64_t y, uint64_t z) {
+  uint64_t x = round_rot(y, y);
+  x = round_rot(x, z);
+  x = round_rot(x, y);
+  uint32_t tl, th;
+  round_norot(x, z, tl, th);                          // t = (th:tl)
+  const uint64_t xr = ((uint64_t)tl << 32) | th;      // rot32(t)
+  const uint32_t r5 = round_hi(xr, y);
+  return ((uint64_t)th << 32) | (tl ^ r5);
+}
+
+// Exact conversions to [0,1): top 24 bits of a squares32 output, top 53 bits
+// of a squares64 output, each scaled by a power of two.
+__device__ __forceinline__ float to_f32(uint32_t u) { return (float)(u >> 8) * 0x1p-24f; }
+__device__ __forceinline__ double to_f64(uint64_t u) { return (double)(u >> 11) * 0x1p-53; }
+
+// Output-kind traits.  Kind numbering matches sq_kind in squares.h.
+template <int K> struct Kind;
+template <> struct Kind<0> { static constexpr int W = 4; };  // U32
+template <> struct Kind<1> { static constexpr int W = 4; };  // F32
+template <> struct Kind<2> { static constexpr int W = 8; };  // U64
+template <> struct Kind<3> { static constexpr int W = 8; };  // F64
+
+// One output of kind K for the counter whose Weyl terms are (y, z), as raw
+// bits (low word first for 8-byte kinds).
+template <int K>
+__device__ __forceinline__ uint64_t gen_bits(uint64_t y, uint64_t z) {
+  if constexpr (K == 0) return sq32(y, z);
+  if constexpr (K == 1) return __float_as_uint(to_f32(sq32(y, z)));
+  if constexpr (K == 2) return sq64(y, z);
+  if constexpr (K == 3) return (uint64_t)__double_as_longlong(to_f64(sq64(y, z)));
+}
+
+// Sixteen bytes of consecutive outputs starting at the counter with first
+// Weyl term y0: four 32-bit outputs or two 64-bit outputs.
+template <int K>
+__device__ __forceinline__ u32x4 gen_vec(uint64_t y0, uint64_t key) {
+  u32x4 o;
+  if constexpr (Kind<K>::W == 4) {
+    const uint64_t y1 = y0 + key, y2 = y1 + key, y3 = y2 + key, y4 = y3 + key;
+    o.x = (uint32_t)gen_bits<K>(y0, y1);
+    o.y = (uint32_t)gen_bits<K>(y1, y2);
+    o.z = (uint32_t)gen_bits<K>(y2, y3);
+    o.w = (uint32_t)gen_bits<K>(y3, y4);
+  } else {
+    const uint64_t y1 = y0 + key, y2 = y1 + key;
+    const uint64_t a = gen_bits<K>(y0, y1), b = gen_bits<K>(y1, y2);
+    o.x = (uint32_t)a; o.y = (uint32_t)(a >> 32);
+    o.z = (uint32_t)b; o.w = (uint32_t)(b >> 32);
+  }
+  return o;
+}
+
+// Writes one output of kind K (element store, for heads and tails).
+template <int K>
+__device__ __forceinline__ void store_one(unsigned char* p, uint64_t y, uint64_t key) {
+  const uint64_t v = gen_bits<K>(y, y + key);
+  if constexpr (Kind<K>::W == 4) *(uint32_t*)p = (uint32_t)v;
+  else *(uint64_t*)p = v;
+}
+
+// The integer a reduce of kind K sums for one output (the value is that
+// integer times 2^-24 for F32 and 2^-53 for F64).
+template <int K>
+__device__ __forceinline__ uint64_t sum_term(uint64_t y, uint64_t z) {
+  if constexpr (K == 0) return sq32(y, z);
+  if constexpr (K == 1) return sq32(y, z) >> 8;
+  if constexpr (K == 2) return sq64(y, z);
+  if constexpr (K == 3) return sq64(y, z) >> 11;
+}
+
+}  // namespace sqd

@@ -1,0 +1,93 @@
+// Internal interfaces shared by the library's translation units (kernels,
+// C ABI, tuner, server).  Not installed; the public interface is squares.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/squares.h"
+
+namespace sqi {
+
+// ---------------------------------------------------------------- errors
+int fail(int status, const std::string& msg);            // records msg, returns status
+int fail_hip(hipError_t e, const char* what);            // SQ_EHIP with the HIP message
+inline int kind_bytes(int kind) { return kind == SQ_U32 || kind == SQ_F32 ? 4 : (kind == SQ_U64 || kind == SQ_F64 ? 8 : 0); }
+
+// ---------------------------------------------------------------- device
+struct DeviceInfo {
+  int device = -1;
+  int cus = 256;
+};
+int ensure_init();                 // binds device info for the current device
+const DeviceInfo& device_info();
+
+// ---------------------------------------------------------------- configs
+bool cfg_valid(sq_op op, const sq_launch_cfg& c);
+sq_launch_cfg default_cfg(sq_op op, int kind, uint64_t n);
+sq_launch_cfg tuned_cfg(sq_op op, int kind, uint64_t n);  // table lookup (default if unset)
+
+// ---------------------------------------------------------------- launches
+hipError_t launch_fill(int kind, uint64_t key, uint64_t ctr0, uint64_t n, void* out,
+                       const sq_launch_cfg& cfg, hipStream_t s);
+
+constexpr uint32_t kReduceMaxParts = 65536;
+hipError_t launch_reduce(int kind, uint64_t key, uint64_t ctr0, uint64_t n, sq_sum_result* out,
+                         void* ws, const sq_launch_cfg& cfg, hipStream_t s);
+
+// Descriptor arrays of a ragged batch (device pointers).
+struct BatchDesc {
+  const uint64_t* keys;
+  const uint64_t* ctr0s;
+  const uint64_t* lens;
+  const uint64_t* offs;
+  const uint8_t* kinds;
+  uint32_t m;
+  unsigned char* out;
+  uint64_t out_bytes;
+};
+
+// Workspace header written by the tile scan; followed by tile_start[m+1].
+struct BatchHdr {
+  uint64_t total_tiles;
+  uint32_t errors;
+  uint32_t m;
+  uint64_t pad[6];
+};
+static_assert(sizeof(BatchHdr) == 64, "header is 64 bytes");
+size_t batch_ws_bytes(uint32_t m);
+hipError_t launch_batch(const BatchDesc& d, void* ws, const sq_launch_cfg& cfg, hipStream_t s);
+
+// Serving tick: entries (slot, first output, count) over a device slot table.
+struct SlotDev {
+  uint64_t key;
+  uint64_t ctr0;
+  uint64_t n;
+  uint64_t out_off;    // byte offset of the request's output in the arena
+  uint64_t done;       // outputs written so far (advanced on the device)
+  uint32_t kind;
+  uint32_t pad;
+};
+static_assert(sizeof(SlotDev) == 48, "slot is 48 bytes");
+struct TickEntry {
+  uint32_t slot;
+  uint32_t pad;
+  uint64_t first;      // first output index within the request
+  uint64_t count;      // outputs in this tick
+};
+static_assert(sizeof(TickEntry) == 24, "tick entry is 24 bytes");
+struct TickHdr {
+  uint32_t entries;    // number of TickEntry that follow
+  uint32_t pad;
+  uint64_t pad2[7];
+};
+static_assert(sizeof(TickHdr) == 64, "tick header is 64 bytes");
+// tick buffer = TickHdr + max_entries TickEntry (device); tick ws holds the
+// expanded batch descriptors and tile scan for up to max_entries streams.
+size_t tick_ws_bytes(uint32_t max_entries);
+hipError_t launch_tick(const void* tick_buf, SlotDev* slots, uint32_t max_entries, unsigned char* arena,
+                       uint64_t arena_bytes, void* tick_ws, const sq_launch_cfg& cfg, hipStream_t s);
+
+}  // namespace sqi

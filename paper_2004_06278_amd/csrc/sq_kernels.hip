@@ -1,0 +1,491 @@
+// gfx950 kernels of the Squares RNG: bulk fill, fused exact reduce, ragged
+// batch (tile scan + persistent fill) and the serving tick expansion.
+//
+// Every kernel is plain VALU integer code (no MFMA: nothing is a
+// contraction).  Fills are bound by HBM write bandwidth: each lane produces
+// 16 bytes (four 32-bit or two 64-bit outputs of consecutive counters) per
+// global_store_dwordx4, so a wave writes 1 KiB contiguous per instruction,
+// and a workgroup writes `block * unroll` such vectors per chunk.  The
+// reduce writes nothing per element; it is bound by the VALU issue rate.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sq_device.hpp"
+#include "sq_internal.hpp"
+
+using namespace sqd;
+
+namespace {
+
+// ============================================================== fill
+struct FillArgs {
+  uint64_t key;
+  uint64_t ctr0;        // counter of element 0
+  unsigned char* out;   // address of element 0 (element-aligned)
+  uint64_t nvec;        // full 16-byte vectors in the aligned body
+  uint64_t nchunks;     // ceil(nvec / (block * U))
+  uint64_t y_body;      // (ctr0 + head) * key: first Weyl term of the body
+  uint64_t ekey;        // E * key: Weyl step from one vector to the next
+  uint32_t head;        // elements before the 16-byte aligned body (0..3)
+  uint32_t tail;        // elements after the last full vector (0..3)
+  uint32_t xcd_map;     // chunk order, see sq_launch_cfg
+  uint32_t pad;
+};
+
+template <int K>
+__device__ __forceinline__ void fill_edges(const FillArgs& a) {
+  constexpr int W = Kind<K>::W, E = 16 / W;
+  const uint32_t t = threadIdx.x;
+  if (blockIdx.x != 0 || t >= a.head + a.tail) return;
+  const uint64_t i = t < a.head ? (uint64_t)t : a.head + a.nvec * E + (t - a.head);
+  store_one<K>(a.out + i * W, (a.ctr0 + i) * a.key, a.key);
+}
+
+// Chunk c covers vectors [c*B*U, (c+1)*B*U) of the body; lane tid writes
+// vectors c*B*U + u*B + tid, u < U (so each store instruction of a wave
+// covers 1 KiB contiguous, and a workgroup's U stores cover B*U*16 bytes).
+template <int K, int U>
+__device__ __forceinline__ void fill_chunk(const FillArgs& a, uint64_t c) {
+  constexpr int W = Kind<K>::W;
+  const uint32_t B = blockDim.x, tid = threadIdx.x;
+  unsigned char* body = a.out + (uint64_t)a.head * W;
+  const uint64_t v0 = c * B * U + tid;
+  uint64_t y = a.y_body + v0 * a.ekey;
+  const uint64_t step = (uint64_t)B * a.ekey;
+  u32x4* p = (u32x4*)(body + v0 * 16);
+  if ((c + 1) * B * U <= a.nvec) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      p[(uint64_t)u * B] = gen_vec<K>(y, a.key);
+      y += step;
+      // one vector's chains at a time: keeps VGPR use low (occupancy hides
+      // the latency of the dependent rounds better than interleaving)
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (v0 + (uint64_t)u * B < a.nvec) p[(uint64_t)u * B] = gen_vec<K>(y, a.key);
+      y += step;
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
+template <int K, int U>
+__global__ __launch_bounds__(1024) void k_fill(FillArgs a) {
+  fill_edges<K>(a);
+  if (a.xcd_map == 0) {
+#pragma unroll 1
+    for (uint64_t c = blockIdx.x; c < a.nchunks; c += gridDim.x) fill_chunk<K, U>(a, c);
+  } else {
+    // Workgroups are dispatched round-robin over the 8 XCDs; give XCD r the
+    // r-th contiguous eighth of the chunks (gridDim.x is a multiple of 8).
+    const uint32_t r = blockIdx.x & 7u, local = blockIdx.x >> 3, gx = gridDim.x >> 3;
+    const uint64_t per = (a.nchunks + 7) / 8;
+    const uint64_t beg = r * per;
+    const uint64_t end = beg + per < a.nchunks ? beg + per : a.nchunks;
+#pragma unroll 1
+    for (uint64_t c = beg + local; c < end; c += gx) fill_chunk<K, U>(a, c);
+  }
+}
+
+typedef void (*FillKernel)(FillArgs);
+template <int K>
+FillKernel fill_kernel_for(uint32_t unroll) {
+  return unroll == 4 ? k_fill<K, 4> : k_fill<K, 8>;
+}
+
+// ============================================================== reduce
+struct ReduceArgs {
+  uint64_t key;
+  uint64_t ctr0;
+  uint64_t n;
+  uint64_t per;          // outputs per thread (contiguous counters)
+  uint64_t* partials;    // 2 x u64 per workgroup
+};
+
+__device__ __forceinline__ void add128(uint64_t& lo, uint64_t& hi, uint64_t v_lo, uint64_t v_hi) {
+  const uint64_t s = lo + v_lo;
+  hi += v_hi + (s < lo);
+  lo = s;
+}
+
+__device__ __forceinline__ void wave_sum128(uint64_t& lo, uint64_t& hi) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t olo = __shfl_xor((unsigned long long)lo, off);
+    const uint64_t ohi = __shfl_xor((unsigned long long)hi, off);
+    add128(lo, hi, olo, ohi);
+  }
+}
+
+// Sum of a workgroup's (lo, hi) pairs into thread 0 (LDS only for the
+// combine across waves).
+__device__ __forceinline__ void block_sum128(uint64_t& lo, uint64_t& hi) {
+  __shared__ uint64_t s_lo[16], s_hi[16];
+  wave_sum128(lo, hi);
+  const uint32_t w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  if ((threadIdx.x & 63) == 0) { s_lo[w] = lo; s_hi[w] = hi; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (uint32_t i = 1; i < nw; ++i) add128(lo, hi, s_lo[i], s_hi[i]);
+  }
+}
+
+// Each thread sums its own contiguous run of counters.  The integer terms
+// are accumulated exactly: in 64 bits over runs short enough not to
+// overflow (FLUSH terms), then into a 128-bit total.
+template <int K, int U>
+__global__ __launch_bounds__(256) void k_reduce(ReduceArgs a) {
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t cnt = 0;
+  if (__umul64hi(t, a.per) == 0 && t * a.per < a.n) {
+    const uint64_t begin = t * a.per;
+    cnt = a.n - begin < a.per ? a.n - begin : a.per;
+  }
+  const uint64_t key = a.key;
+  uint64_t y = (a.ctr0 + t * a.per) * key;
+  uint64_t lo = 0, hi = 0;
+  if constexpr (K == 2) {
+    // 64-bit terms: carry into the high word after every term
+    uint64_t i = 0;
+    for (; i + U <= cnt; i += U) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint64_t z = y + key;
+        add128(lo, hi, sum_term<K>(y, z), 0);
+        y = z;
+      }
+    }
+    for (; i < cnt; ++i) {
+      const uint64_t z = y + key;
+      add128(lo, hi, sum_term<K>(y, z), 0);
+      y = z;
+    }
+  } else {
+    // terms < 2^53 (F64), < 2^32 (U32), < 2^24 (F32)
+    constexpr uint64_t FLUSH = K == 3 ? 1024 : (1u << 20);
+    uint64_t i = 0;
+    while (i < cnt) {
+      const uint64_t len = cnt - i < FLUSH ? cnt - i : FLUSH;
+      uint64_t s = 0, j = 0;
+      for (; j + U <= len; j += U) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const uint64_t z = y + key;
+          s += sum_term<K>(y, z);
+          y = z;
+        }
+      }
+      for (; j < len; ++j) {
+        const uint64_t z = y + key;
+        s += sum_term<K>(y, z);
+        y = z;
+      }
+      add128(lo, hi, s, 0);
+      i += len;
+    }
+  }
+  block_sum128(lo, hi);
+  if (threadIdx.x == 0) {
+    a.partials[2 * blockIdx.x] = lo;
+    a.partials[2 * blockIdx.x + 1] = hi;
+  }
+}
+
+// Nearest double (ties to even) of the 128-bit integer S times 2^e.
+__device__ double round_scaled(uint64_t lo, uint64_t hi, int e) {
+  if (hi == 0 && lo < (1ull << 53)) return ldexp((double)lo, e);
+  const int msb = hi ? 127 - __clzll((long long)hi) : 63 - __clzll((long long)lo);
+  int s = msb - 52;  // bits dropped, >= 1
+  const unsigned __int128 S = ((unsigned __int128)hi << 64) | lo;
+  uint64_t mant = (uint64_t)(S >> s);
+  const unsigned __int128 rem = S & ((((unsigned __int128)1) << s) - 1);
+  const unsigned __int128 half = ((unsigned __int128)1) << (s - 1);
+  if (rem > half || (rem == half && (mant & 1))) {
+    ++mant;
+    if (mant == (1ull << 53)) { mant >>= 1; ++s; }
+  }
+  return ldexp((double)mant, s + e);
+}
+
+__global__ __launch_bounds__(256) void k_reduce_final(const uint64_t* partials, uint32_t nparts, uint64_t n, int e,
+                                                      sq_sum_result* out) {
+  uint64_t lo = 0, hi = 0;
+  for (uint32_t i = threadIdx.x; i < nparts; i += blockDim.x) add128(lo, hi, partials[2 * i], partials[2 * i + 1]);
+  block_sum128(lo, hi);
+  if (threadIdx.x == 0) {
+    out->lo = lo;
+    out->hi = hi;
+    out->value = round_scaled(lo, hi, e);
+    out->n = n;
+  }
+}
+
+typedef void (*ReduceKernel)(ReduceArgs);
+template <int K>
+ReduceKernel reduce_kernel_for(uint32_t unroll) {
+  switch (unroll) {
+    case 1: return k_reduce<K, 1>;
+    case 2: return k_reduce<K, 2>;
+    default: return k_reduce<K, 4>;
+  }
+}
+
+// ============================================================== batch
+// Tiles of stream s under tile size 2^lg, or 0 (and *bad = 1) when the
+// descriptor is invalid: unknown kind, offset not a multiple of the element
+// size, or a range past the arena.
+__device__ __forceinline__ uint64_t stream_tiles(const sqi::BatchDesc& d, uint32_t s, uint32_t lg, uint32_t* bad) {
+  const uint32_t kind = d.kinds[s];
+  const uint64_t len = d.lens[s], off = d.offs[s];
+  const uint32_t W = kind < 2 ? 4u : 8u;
+  if (kind > 3 || (off & (W - 1)) != 0 || off > d.out_bytes || len > (d.out_bytes - off) / W) {
+    *bad += 1;
+    return 0;
+  }
+  return (len >> lg) + ((len & ((1ull << lg) - 1)) != 0);
+}
+
+// One workgroup: exclusive scan of per-stream tile counts into ts[0..m],
+// plus the total and the count of skipped streams in the header.
+__global__ __launch_bounds__(1024) void k_batch_scan(sqi::BatchDesc d, const uint32_t* m_dev, uint32_t lg,
+                                                     sqi::BatchHdr* hdr, uint64_t* ts) {
+  __shared__ uint64_t part[1024];
+  __shared__ uint32_t errs;
+  const uint32_t m = m_dev ? *m_dev : d.m;
+  const uint32_t tid = threadIdx.x, B = blockDim.x;
+  const uint32_t per = (m + B - 1) / B;
+  const uint32_t b = tid * per < m ? tid * per : m;
+  const uint32_t e = b + per < m ? b + per : m;
+  if (tid == 0) errs = 0;
+  __syncthreads();
+  uint64_t local = 0;
+  uint32_t bad = 0;
+  for (uint32_t s = b; s < e; ++s) local += stream_tiles(d, s, lg, &bad);
+  part[tid] = local;
+  if (bad) atomicAdd(&errs, bad);
+  __syncthreads();
+  for (uint32_t off = 1; off < B; off <<= 1) {
+    const uint64_t v = tid >= off ? part[tid - off] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  uint64_t run = tid ? part[tid - 1] : 0;
+  uint32_t dummy = 0;
+  for (uint32_t s = b; s < e; ++s) {
+    ts[s] = run;
+    run += stream_tiles(d, s, lg, &dummy);
+  }
+  if (tid == B - 1) {
+    ts[m] = part[B - 1];
+    hdr->total_tiles = part[B - 1];
+    hdr->m = m;
+    hdr->errors = errs;
+  }
+}
+
+// The workgroup fills `cnt` outputs of kind K from counter ctr at p
+// (element-aligned): a head up to the next 16-byte boundary, full vectors,
+// and a tail, element stores at both ends.
+template <int K>
+__device__ __forceinline__ void fill_range(uint64_t key, uint64_t ctr, uint64_t cnt, unsigned char* p) {
+  constexpr int W = Kind<K>::W, E = 16 / W;
+  const uint32_t tid = threadIdx.x, B = blockDim.x;
+  const uint32_t mis = (uint32_t)((uintptr_t)p & 15u);
+  uint64_t head = mis ? (16u - mis) / W : 0;
+  if (head > cnt) head = cnt;
+  const uint64_t nvec = (cnt - head) / E;
+  const uint64_t tail = cnt - head - nvec * E;
+  if (tid < head) store_one<K>(p + (uint64_t)tid * W, (ctr + tid) * key, key);
+  if (tid < tail) {
+    const uint64_t i = head + nvec * E + tid;
+    store_one<K>(p + i * W, (ctr + i) * key, key);
+  }
+  unsigned char* body = p + head * W;
+  const uint64_t ekey = (uint64_t)E * key;
+  uint64_t y = (ctr + head + (uint64_t)tid * E) * key;
+  const uint64_t step = (uint64_t)B * ekey;
+#pragma unroll 1
+  for (uint64_t v = tid; v < nvec; v += B) {
+    *(u32x4*)(body + v * 16) = gen_vec<K>(y, key);
+    y += step;
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// Persistent: workgroup g takes tiles g, g + grid, ...; each tile is mapped
+// to its stream by binary search over the tile scan (wave-uniform, so the
+// loads go through the scalar cache).
+__global__ __launch_bounds__(1024) void k_batch_fill(sqi::BatchDesc d, uint32_t lg, const sqi::BatchHdr* hdr,
+                                                     const uint64_t* ts) {
+  const uint64_t total = hdr->total_tiles;
+  const uint32_t m = hdr->m;
+  const uint64_t T = 1ull << lg;
+#pragma unroll 1
+  for (uint64_t t = blockIdx.x; t < total; t += gridDim.x) {
+    uint32_t lo = 0, hi = m - 1;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (ts[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    const uint32_t s = lo;
+    const uint64_t off = (t - ts[s]) << lg;
+    const uint64_t len = d.lens[s];
+    const uint64_t cnt = len - off < T ? len - off : T;
+    const uint32_t kind = d.kinds[s];
+    const uint64_t key = d.keys[s], ctr = d.ctr0s[s] + off;
+    unsigned char* p = d.out + d.offs[s] + off * (kind < 2 ? 4u : 8u);
+    switch (kind) {
+      case 0: fill_range<0>(key, ctr, cnt, p); break;
+      case 1: fill_range<1>(key, ctr, cnt, p); break;
+      case 2: fill_range<2>(key, ctr, cnt, p); break;
+      default: fill_range<3>(key, ctr, cnt, p); break;
+    }
+  }
+}
+
+// ============================================================== serving tick
+// Expands the tick's (slot, first, count) entries into batch descriptors
+// and advances each slot's device-side progress counter.
+__global__ __launch_bounds__(256) void k_tick_expand(const sqi::TickHdr* th, const sqi::TickEntry* ent,
+                                                     sqi::SlotDev* slots, uint64_t* keys, uint64_t* ctr0s,
+                                                     uint64_t* lens, uint64_t* offs, uint8_t* kinds,
+                                                     uint32_t* m_out, uint32_t max_entries) {
+  const uint32_t m = th->entries < max_entries ? th->entries : max_entries;
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *m_out = m;
+  if (i >= m) return;
+  const sqi::TickEntry e = ent[i];
+  sqi::SlotDev& s = slots[e.slot];
+  const uint32_t W = s.kind < 2 ? 4u : 8u;
+  keys[i] = s.key;
+  ctr0s[i] = s.ctr0 + e.first;
+  lens[i] = e.count;
+  offs[i] = s.out_off + e.first * W;
+  kinds[i] = (uint8_t)s.kind;
+  atomicAdd((unsigned long long*)&s.done, (unsigned long long)e.count);
+}
+
+}  // namespace
+
+// ============================================================== launchers
+namespace sqi {
+
+hipError_t launch_fill(int kind, uint64_t key, uint64_t ctr0, uint64_t n, void* out, const sq_launch_cfg& cfg,
+                       hipStream_t s) {
+  const int W = kind_bytes(kind), E = 16 / W;
+  FillArgs a{};
+  a.key = key;
+  a.ctr0 = ctr0;
+  a.out = (unsigned char*)out;
+  const uint32_t mis = (uint32_t)((uintptr_t)out & 15u);
+  uint64_t head = mis ? (16u - mis) / W : 0;
+  if (head > n) head = n;
+  a.head = (uint32_t)head;
+  a.nvec = (n - head) / E;
+  a.tail = (uint32_t)(n - head - a.nvec * E);
+  const uint64_t per_chunk = (uint64_t)cfg.block * cfg.unroll;
+  a.nchunks = (a.nvec + per_chunk - 1) / per_chunk;
+  a.y_body = (ctr0 + head) * key;
+  a.ekey = (uint64_t)E * key;
+  uint64_t grid = (uint64_t)device_info().cus * cfg.grid_per_cu;
+  if (grid > a.nchunks) grid = a.nchunks;
+  a.xcd_map = cfg.xcd_map;
+  if (a.xcd_map && grid >= 8) grid &= ~7ull;  // XCD-contiguous order needs a multiple of 8
+  else a.xcd_map = 0;
+  if (grid == 0) grid = 1;                      // the head/tail elements still need a workgroup
+  FillKernel k = nullptr;
+  switch (kind) {
+    case SQ_U32: k = fill_kernel_for<0>(cfg.unroll); break;
+    case SQ_F32: k = fill_kernel_for<1>(cfg.unroll); break;
+    case SQ_U64: k = fill_kernel_for<2>(cfg.unroll); break;
+    default: k = fill_kernel_for<3>(cfg.unroll); break;
+  }
+  hipLaunchKernelGGL(k, dim3((uint32_t)grid), dim3(cfg.block), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(int kind, uint64_t key, uint64_t ctr0, uint64_t n, sq_sum_result* out, void* ws,
+                         const sq_launch_cfg& cfg, hipStream_t s) {
+  const uint32_t B = 256;  // reduce workgroups are 256 threads (block_sum128 LDS sized for <= 1024)
+  uint64_t grid = (uint64_t)device_info().cus * cfg.grid_per_cu;
+  const uint64_t need = (n + B - 1) / B;  // at least one output per thread
+  if (grid > need) grid = need;
+  if (grid == 0) grid = 1;
+  if (grid > kReduceMaxParts) grid = kReduceMaxParts;
+  const uint64_t T = grid * B;
+  ReduceArgs a{};
+  a.key = key;
+  a.ctr0 = ctr0;
+  a.n = n;
+  a.per = n / T + (n % T != 0);
+  a.partials = (uint64_t*)ws;
+  ReduceKernel k = nullptr;
+  switch (kind) {
+    case SQ_U32: k = reduce_kernel_for<0>(cfg.unroll); break;
+    case SQ_F32: k = reduce_kernel_for<1>(cfg.unroll); break;
+    case SQ_U64: k = reduce_kernel_for<2>(cfg.unroll); break;
+    default: k = reduce_kernel_for<3>(cfg.unroll); break;
+  }
+  hipLaunchKernelGGL(k, dim3((uint32_t)grid), dim3(B), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int scale = kind == SQ_F32 ? -24 : (kind == SQ_F64 ? -53 : 0);
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, (const uint64_t*)ws, (uint32_t)grid, n, scale, out);
+  return hipGetLastError();
+}
+
+size_t batch_ws_bytes(uint32_t m) {
+  const size_t b = sizeof(BatchHdr) + 8ull * ((size_t)m + 1);
+  return (b + 255) & ~(size_t)255;
+}
+
+static hipError_t launch_batch_body(const BatchDesc& d, const uint32_t* m_dev, void* ws, const sq_launch_cfg& cfg,
+                                    hipStream_t s) {
+  BatchHdr* hdr = (BatchHdr*)ws;
+  uint64_t* ts = (uint64_t*)((unsigned char*)ws + sizeof(BatchHdr));
+  hipLaunchKernelGGL(k_batch_scan, dim3(1), dim3(1024), 0, s, d, m_dev, cfg.tile_log2, hdr, ts);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const uint32_t grid = (uint32_t)device_info().cus * cfg.grid_per_cu;
+  hipLaunchKernelGGL(k_batch_fill, dim3(grid), dim3(cfg.block), 0, s, d, cfg.tile_log2, (const BatchHdr*)hdr,
+                     (const uint64_t*)ts);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchDesc& d, void* ws, const sq_launch_cfg& cfg, hipStream_t s) {
+  return launch_batch_body(d, nullptr, ws, cfg, s);
+}
+
+// tick ws layout: keys, ctr0s, lens, offs (u64 x max each), kinds (u8 x max,
+// padded), m (u32, padded to 256), then the batch workspace.
+size_t tick_ws_bytes(uint32_t max_entries) {
+  const size_t arrays = 32ull * max_entries + (((size_t)max_entries + 255) & ~(size_t)255) + 256;
+  return arrays + batch_ws_bytes(max_entries);
+}
+
+hipError_t launch_tick(const void* tick_buf, SlotDev* slots, uint32_t max_entries, unsigned char* arena,
+                       uint64_t arena_bytes, void* tick_ws, const sq_launch_cfg& cfg, hipStream_t s) {
+  unsigned char* w = (unsigned char*)tick_ws;
+  uint64_t* keys = (uint64_t*)w;
+  uint64_t* ctr0s = keys + max_entries;
+  uint64_t* lens = ctr0s + max_entries;
+  uint64_t* offs = lens + max_entries;
+  uint8_t* kinds = (uint8_t*)(offs + max_entries);
+  uint32_t* m_dev = (uint32_t*)(kinds + (((size_t)max_entries + 255) & ~(size_t)255));
+  void* bws = (unsigned char*)m_dev + 256;
+  const TickHdr* th = (const TickHdr*)tick_buf;
+  const TickEntry* ent = (const TickEntry*)((const unsigned char*)tick_buf + sizeof(TickHdr));
+  const uint32_t blocks = (max_entries + 255) / 256;
+  hipLaunchKernelGGL(k_tick_expand, dim3(blocks), dim3(256), 0, s, th, ent, slots, keys, ctr0s, lens, offs, kinds,
+                     m_dev, max_entries);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  BatchDesc d{keys, ctr0s, lens, offs, kinds, max_entries, arena, arena_bytes};
+  return launch_batch_body(d, m_dev, bws, cfg, s);
+}
+
+}  // namespace sqi

@@ -1,0 +1,388 @@
+// Launch-configuration table and the autotuner.
+//
+// The table holds one sq_launch_cfg per (op, kind, size bucket).  The
+// autotuner times every candidate configuration with HIP events on scratch
+// buffers it allocates itself, and accepts a candidate only if its output is
+// bit-identical to the default configuration's output (a device compare),
+// so a tuned table can never change results.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "sq_internal.hpp"
+
+namespace sqi {
+
+static constexpr int kOps = 3, kKinds = 4, kBuckets = 5;
+
+struct Entry {
+  sq_launch_cfg cfg;
+  bool set;
+};
+static std::mutex g_tab_mu;
+static Entry g_tab[kOps][kKinds][kBuckets];
+static bool g_autoloaded = false;
+
+static int bucket_of(uint64_t n) {
+  if (n < (1ull << 16)) return 0;
+  if (n < (1ull << 20)) return 1;
+  if (n < (1ull << 24)) return 2;
+  if (n < (1ull << 28)) return 3;
+  return 4;
+}
+
+static bool in(uint32_t v, std::initializer_list<uint32_t> set) {
+  return std::find(set.begin(), set.end(), v) != set.end();
+}
+
+bool cfg_valid(sq_op op, const sq_launch_cfg& c) {
+  if (c.grid_per_cu < 1 || c.grid_per_cu > 64) return false;
+  switch (op) {
+    case SQ_OP_FILL:
+      return in(c.block, {256, 512, 1024}) && in(c.unroll, {4, 8}) && c.xcd_map <= 1;
+    case SQ_OP_REDUCE:
+      return in(c.unroll, {1, 2, 4});
+    case SQ_OP_BATCH:
+      return in(c.block, {256, 512, 1024}) && c.tile_log2 >= 12 && c.tile_log2 <= 24;
+  }
+  return false;
+}
+
+sq_launch_cfg default_cfg(sq_op op, int kind, uint64_t n) {
+  (void)n;
+  switch (op) {
+    case SQ_OP_FILL: return sq_launch_cfg{1024, kind_bytes(kind) == 4 ? 8u : 4u, 16, 0, 16};
+    case SQ_OP_REDUCE: return sq_launch_cfg{256, 2, 8, 0, 16};
+    default: return sq_launch_cfg{512, 1, 4, 0, 16};
+  }
+}
+
+sq_launch_cfg tuned_cfg(sq_op op, int kind, uint64_t n) {
+  std::lock_guard<std::mutex> g(g_tab_mu);
+  const Entry& e = g_tab[op][kind & 3][bucket_of(n)];
+  return e.set ? e.cfg : default_cfg(op, kind, n);
+}
+
+static int load_file(const char* path) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return fail(SQ_ENOTFOUND, std::string("cannot open tuning table ") + path);
+  char line[512];
+  int loaded = 0;
+  std::vector<std::pair<int, Entry>> rows;
+  int op, kind, bucket;
+  unsigned block, unroll, gpc, xcd, tile;
+  while (std::fgets(line, sizeof line, f)) {
+    if (std::sscanf(line,
+                    " {\"op\": %d, \"kind\": %d, \"bucket\": %d, \"block\": %u, \"unroll\": %u, \"grid_per_cu\": %u, "
+                    "\"xcd_map\": %u, \"tile_log2\": %u",
+                    &op, &kind, &bucket, &block, &unroll, &gpc, &xcd, &tile) == 8) {
+      if (op < 0 || op >= kOps || kind < 0 || kind >= kKinds || bucket < 0 || bucket >= kBuckets) continue;
+      sq_launch_cfg c{block, unroll, gpc, xcd, tile};
+      if (!cfg_valid((sq_op)op, c)) continue;
+      rows.push_back({(op * kKinds + kind) * kBuckets + bucket, Entry{c, true}});
+      ++loaded;
+    }
+  }
+  std::fclose(f);
+  std::lock_guard<std::mutex> g(g_tab_mu);
+  for (auto& r : rows) (&g_tab[0][0][0])[r.first] = r.second;
+  return SQ_OK;
+}
+
+int tune_autoload() {
+  {
+    std::lock_guard<std::mutex> g(g_tab_mu);
+    if (g_autoloaded) return SQ_OK;
+    g_autoloaded = true;
+  }
+  const char* p = std::getenv("SQ_TUNE_CACHE");
+  if (p && *p) (void)load_file(p);  // a missing cache leaves the defaults
+  return SQ_OK;
+}
+
+// ---------------------------------------------------------------- compare kernel
+__global__ void k_count_diff(const uint32_t* a, const uint32_t* b, uint64_t words, unsigned long long* bad) {
+  uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  const uint64_t G = (uint64_t)gridDim.x * blockDim.x;
+  unsigned long long c = 0;
+  for (; i < words; i += G) c += a[i] != b[i];
+  if (c) atomicAdd(bad, c);
+}
+
+struct Scratch {
+  void* a = nullptr;
+  void* b = nullptr;
+  unsigned long long* bad = nullptr;
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ~Scratch() {
+    if (a) (void)hipFree(a);
+    if (b) (void)hipFree(b);
+    if (bad) (void)hipFree(bad);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (s) (void)hipStreamDestroy(s);
+  }
+};
+
+static hipError_t same_bytes(Scratch& S, uint64_t bytes, bool* same) {
+  hipError_t e = hipMemsetAsync(S.bad, 0, sizeof(unsigned long long), S.s);
+  if (e != hipSuccess) return e;
+  const uint64_t words = bytes / 4;
+  hipLaunchKernelGGL(k_count_diff, dim3(device_info().cus * 8), dim3(256), 0, S.s, (const uint32_t*)S.a,
+                     (const uint32_t*)S.b, words, S.bad);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  unsigned long long h = 1;
+  e = hipMemcpyAsync(&h, S.bad, sizeof h, hipMemcpyDeviceToHost, S.s);
+  if (e == hipSuccess) e = hipStreamSynchronize(S.s);
+  *same = (h == 0);
+  return e;
+}
+
+template <typename F>
+static hipError_t time_best(Scratch& S, F launch, int reps, float* best_ms) {
+  hipError_t e = launch();  // warm-up
+  if (e != hipSuccess) return e;
+  float best = 1e30f;
+  for (int r = 0; r < reps; ++r) {
+    if ((e = hipEventRecord(S.e0, S.s)) != hipSuccess) return e;
+    if ((e = launch()) != hipSuccess) return e;
+    if ((e = hipEventRecord(S.e1, S.s)) != hipSuccess) return e;
+    if ((e = hipEventSynchronize(S.e1)) != hipSuccess) return e;
+    float ms = 0;
+    if ((e = hipEventElapsedTime(&ms, S.e0, S.e1)) != hipSuccess) return e;
+    best = std::min(best, ms);
+  }
+  *best_ms = best;
+  return hipSuccess;
+}
+
+static void set_entry(int op, int kind, int bucket, const sq_launch_cfg& c) {
+  std::lock_guard<std::mutex> g(g_tab_mu);
+  g_tab[op][kind][bucket] = Entry{c, true};
+}
+
+// Deterministic generator for the tuner's own synthetic batch descriptors.
+static uint64_t splitmix(uint64_t& s) {
+  uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+}  // namespace sqi
+
+using namespace sqi;
+
+extern "C" {
+
+int sq_tune_get(sq_op op, sq_kind kind, uint64_t n, sq_launch_cfg* cfg) {
+  if (cfg == nullptr || (int)op < 0 || (int)op >= kOps || kind_bytes(kind) == 0)
+    return fail(SQ_EINVAL, "bad tune_get arguments");
+  *cfg = tuned_cfg(op, kind, n);
+  return SQ_OK;
+}
+
+int sq_tune_set(sq_op op, sq_kind kind, uint64_t n, const sq_launch_cfg* cfg) {
+  if (cfg == nullptr || (int)op < 0 || (int)op >= kOps || kind_bytes(kind) == 0)
+    return fail(SQ_EINVAL, "bad tune_set arguments");
+  if (!cfg_valid(op, *cfg)) return fail(SQ_EINVAL, "invalid launch configuration");
+  set_entry(op, kind, bucket_of(n), *cfg);
+  return SQ_OK;
+}
+
+int sq_tune_load(const char* path) {
+  if (path == nullptr) return fail(SQ_EINVAL, "null path");
+  return load_file(path);
+}
+
+int sq_tune_save(const char* path) {
+  if (path == nullptr) return fail(SQ_EINVAL, "null path");
+  FILE* f = std::fopen(path, "w");
+  if (!f) return fail(SQ_EINVAL, std::string("cannot write ") + path);
+  std::lock_guard<std::mutex> g(g_tab_mu);
+  std::fprintf(f, "[\n");
+  bool first = true;
+  for (int op = 0; op < kOps; ++op)
+    for (int k = 0; k < kKinds; ++k)
+      for (int b = 0; b < kBuckets; ++b) {
+        const Entry& e = g_tab[op][k][b];
+        if (!e.set) continue;
+        std::fprintf(f,
+                     "%s {\"op\": %d, \"kind\": %d, \"bucket\": %d, \"block\": %u, \"unroll\": %u, \"grid_per_cu\": "
+                     "%u, \"xcd_map\": %u, \"tile_log2\": %u}",
+                     first ? "" : ",\n", op, k, b, e.cfg.block, e.cfg.unroll, e.cfg.grid_per_cu, e.cfg.xcd_map,
+                     e.cfg.tile_log2);
+        first = false;
+      }
+  std::fprintf(f, "\n]\n");
+  std::fclose(f);
+  return SQ_OK;
+}
+
+int sq_autotune(uint32_t op_mask, uint64_t max_bytes, const char* save_path) {
+  int rc = ensure_init();
+  if (rc != SQ_OK) return rc;
+  const uint64_t half = std::max<uint64_t>(max_bytes / 2, 16ull << 20) & ~(uint64_t)0xFFFF;
+  Scratch S;
+  hipError_t e = hipMalloc(&S.a, half);
+  if (e == hipSuccess) e = hipMalloc(&S.b, half);
+  if (e == hipSuccess) e = hipMalloc((void**)&S.bad, 64);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&S.s, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreate(&S.e0);
+  if (e == hipSuccess) e = hipEventCreate(&S.e1);
+  if (e != hipSuccess) return fail_hip(e, "autotune scratch allocation");
+  const uint64_t key = 0x9B2F6E1D4C8A0357ull, ctr0 = 0xFFFFFFFFFFFF0000ull;  // crosses 2^64 on purpose
+
+  if (op_mask & (1u << SQ_OP_FILL)) {
+    for (int kind = 0; kind < kKinds; ++kind) {
+      const uint64_t W = kind_bytes(kind);
+      for (int b = 0; b < kBuckets; ++b) {
+        uint64_t n = std::min<uint64_t>(1ull << (4 * b + 15), half / W);
+        n -= 3;  // ragged: exercises the tail
+        const sq_launch_cfg ref = default_cfg(SQ_OP_FILL, kind, n);
+        // outputs start 4 bytes in (a misaligned head); zero the bytes before them
+        if ((e = hipMemsetAsync(S.a, 0, 256, S.s)) != hipSuccess) break;
+        if ((e = hipMemsetAsync(S.b, 0, 256, S.s)) != hipSuccess) break;
+        if ((e = launch_fill(kind, key, ctr0, n, (unsigned char*)S.b + 4, ref, S.s)) != hipSuccess) break;
+        std::swap(S.a, S.b);  // reference now in a (at +4)
+        float best = 1e30f;
+        sq_launch_cfg best_c = ref;
+        for (uint32_t blk : {256u, 512u, 1024u})
+          for (uint32_t u : {4u, 8u})
+            for (uint32_t g : {4u, 8u, 16u, 32u})
+              for (uint32_t x : {0u, 1u}) {
+                sq_launch_cfg c{blk, u, g, x, 16};
+                float ms = 0;
+                e = time_best(S, [&] { return launch_fill(kind, key, ctr0, n, (unsigned char*)S.b + 4, c, S.s); },
+                              3, &ms);
+                if (e != hipSuccess) break;
+                bool same = false;
+                if ((e = same_bytes(S, n * W + 4, &same)) != hipSuccess) break;
+                if (same && ms < best) { best = ms; best_c = c; }
+              }
+        if (e != hipSuccess) break;
+        set_entry(SQ_OP_FILL, kind, b, best_c);
+      }
+      if (e != hipSuccess) break;
+    }
+    if (e != hipSuccess) return fail_hip(e, "autotune fill");
+  }
+
+  if (op_mask & (1u << SQ_OP_REDUCE)) {
+    sq_sum_result* res = (sq_sum_result*)S.a;        // reference result
+    sq_sum_result* cand = (sq_sum_result*)S.b;       // candidate result
+    void* ws = (unsigned char*)S.b + 4096;
+    for (int kind = 0; kind < kKinds && e == hipSuccess; ++kind) {
+      for (int b = 0; b < kBuckets && e == hipSuccess; ++b) {
+        const uint64_t n = (1ull << (4 * b + 15)) - 5;
+        const sq_launch_cfg ref = default_cfg(SQ_OP_REDUCE, kind, n);
+        if ((e = launch_reduce(kind, key, ctr0, n, res, ws, ref, S.s)) != hipSuccess) break;
+        float best = 1e30f;
+        sq_launch_cfg best_c = ref;
+        for (uint32_t u : {1u, 2u, 4u})
+          for (uint32_t g : {2u, 4u, 8u, 16u, 32u}) {
+            sq_launch_cfg c{256, u, g, 0, 16};
+            float ms = 0;
+            e = time_best(S, [&] { return launch_reduce(kind, key, ctr0, n, cand, ws, c, S.s); }, 3, &ms);
+            if (e != hipSuccess) break;
+            sq_sum_result h[2];
+            if ((e = hipMemcpyAsync(&h[0], res, sizeof h[0], hipMemcpyDeviceToHost, S.s)) != hipSuccess) break;
+            if ((e = hipMemcpyAsync(&h[1], cand, sizeof h[1], hipMemcpyDeviceToHost, S.s)) != hipSuccess) break;
+            if ((e = hipStreamSynchronize(S.s)) != hipSuccess) break;
+            if (std::memcmp(&h[0], &h[1], sizeof h[0]) == 0 && ms < best) { best = ms; best_c = c; }
+          }
+        if (e == hipSuccess) set_entry(SQ_OP_REDUCE, kind, b, best_c);
+      }
+    }
+    if (e != hipSuccess) return fail_hip(e, "autotune reduce");
+  }
+
+  if (op_mask & (1u << SQ_OP_BATCH)) {
+    // Synthetic ragged batches: log-uniform lengths around each bucket,
+    // all four kinds, packed back to back (8-byte aligned).
+    for (int b = 0; b < kBuckets && e == hipSuccess; ++b) {
+      const double lo_e = 4.0 * b + 8, hi_e = 4.0 * b + 12;
+      const uint64_t budget = half - (1ull << 20);
+      std::vector<uint64_t> keys, ctrs, lens, offs;
+      std::vector<uint8_t> kinds;
+      uint64_t rng = 12345 + b, pos = 0;
+      while (keys.size() < 4096) {
+        const double u = (double)(splitmix(rng) >> 11) * 0x1p-53;
+        const uint64_t len = (uint64_t)std::exp2(lo_e + (hi_e - lo_e) * u);
+        const uint8_t kd = (uint8_t)(splitmix(rng) & 3);
+        const uint64_t W = kd < 2 ? 4 : 8;
+        pos = (pos + 7) & ~7ull;
+        if (pos + len * W > budget) break;
+        keys.push_back(splitmix(rng));
+        ctrs.push_back(splitmix(rng));
+        lens.push_back(len);
+        offs.push_back(pos);
+        kinds.push_back(kd);
+        pos += len * W;
+      }
+      const uint32_t m = (uint32_t)keys.size();
+      if (m == 0) continue;
+      // descriptors live in a's tail region (after the arena) in both buffers' roles:
+      // the arena is [0, budget) of a/b, descriptors + workspace follow in a separate allocation
+      void* desc = nullptr;
+      const size_t dbytes = 33ull * m + 64 + batch_ws_bytes(m) + 4096;
+      if ((e = hipMalloc(&desc, dbytes)) != hipSuccess) break;
+      uint64_t* dk = (uint64_t*)desc;
+      uint64_t* dc = dk + m;
+      uint64_t* dl = dc + m;
+      uint64_t* dof = dl + m;
+      uint8_t* dkd = (uint8_t*)(dof + m);
+      void* ws = (void*)(((uintptr_t)(dkd + m) + 255) & ~(uintptr_t)255);
+      e = hipMemcpy(dk, keys.data(), 8ull * m, hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = hipMemcpy(dc, ctrs.data(), 8ull * m, hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = hipMemcpy(dl, lens.data(), 8ull * m, hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = hipMemcpy(dof, offs.data(), 8ull * m, hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = hipMemcpy(dkd, kinds.data(), m, hipMemcpyHostToDevice);
+      const uint64_t used = (pos + 255) & ~255ull;
+      if (e == hipSuccess) e = hipMemsetAsync(S.a, 0, used, S.s);
+      if (e == hipSuccess) e = hipMemsetAsync(S.b, 0, used, S.s);
+      const sq_launch_cfg ref = default_cfg(SQ_OP_BATCH, 0, 0);
+      if (e == hipSuccess) {
+        BatchDesc d{dk, dc, dl, dof, dkd, m, (unsigned char*)S.a, budget};
+        e = launch_batch(d, ws, ref, S.s);
+      }
+      float best = 1e30f;
+      sq_launch_cfg best_c = ref;
+      for (uint32_t tl : {14u, 16u, 18u, 20u}) {
+        for (uint32_t blk : {256u, 512u, 1024u}) {
+          for (uint32_t g : {2u, 4u, 8u, 16u}) {
+            if (e != hipSuccess) break;
+            sq_launch_cfg c{blk, 1, g, 0, tl};
+            BatchDesc d{dk, dc, dl, dof, dkd, m, (unsigned char*)S.b, budget};
+            float ms = 0;
+            e = time_best(S, [&] { return launch_batch(d, ws, c, S.s); }, 3, &ms);
+            if (e != hipSuccess) break;
+            bool same = false;
+            if ((e = same_bytes(S, used, &same)) != hipSuccess) break;
+            if (same && ms < best) { best = ms; best_c = c; }
+          }
+        }
+      }
+      hipError_t fe = hipFree(desc);
+      if (e == hipSuccess) e = fe;
+      if (e == hipSuccess) {
+        for (int k = 0; k < kKinds; ++k) set_entry(SQ_OP_BATCH, k, b, best_c);
+      }
+    }
+    if (e != hipSuccess) return fail_hip(e, "autotune batch");
+  }
+  if (save_path) return sq_tune_save(save_path);
+  return SQ_OK;
+}
+
+}  // extern "C"

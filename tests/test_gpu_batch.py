@@ -1,0 +1,164 @@
+"""GPU parity of the ragged batch (tile scan + persistent kernel), its graph
+plan, and descriptor validation."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from gpu_helpers import KIND_BYTES, compare_batch_arena, first_diff, log, to_host_bytes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sq():
+    from paper_2004_06278_amd import squares
+
+    squares.lib()
+    return squares
+
+
+def _oracle_arena(o, b):
+    return o.fill_batch(b.keys, b.ctr0s, b.lens, b.offs, b.kinds, b.arena_bytes)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_batch_small_random(sq, oracle_mod, seed):
+    """Mixed kinds, empty streams, misaligned starts, counters near 2^64,
+    zero and even keys; several tile sizes so streams span many tiles."""
+    from paper_2004_06278_amd import workloads as W
+
+    b = W.small_random_batch(seed=seed, m=300, max_len=20000)
+    ref = _oracle_arena(oracle_mod, b)
+    db = sq.batch_to_device(b.keys, b.ctr0s, b.lens, b.offs, b.kinds, b.arena_bytes)
+    for tl in (12, 13, 16, 24):
+        for block in (256, 1024):
+            for gpc in (1, 8):
+                c = sq.cfg(block=block, grid_per_cu=gpc, tile_log2=tl)
+                log(f"batch seed={seed} m={b.m} cfg={c.as_dict()}")
+                db.out.zero_()
+                sq.fill_batch(db, launch_cfg=c)
+                got = to_host_bytes(db.out)[: b.arena_bytes]
+                assert got.tobytes() == ref.tobytes(), (c.as_dict(), first_diff(got, ref))
+                assert sq.batch_errors(db) == 0
+
+
+def test_batch_equals_per_stream_fills(sq):
+    """Each stream of a batch is bit-identical to a standalone sq_fill of the
+    same (kind, key, ctr0, len)."""
+    import torch
+
+    from paper_2004_06278_amd import workloads as W
+
+    b = W.small_random_batch(seed=9, m=150, max_len=50000)
+    db = sq.batch_to_device(b.keys, b.ctr0s, b.lens, b.offs, b.kinds, b.arena_bytes)
+    sq.fill_batch(db)
+    arena = to_host_bytes(db.out)
+    for s in range(b.m):
+        k, L, off = int(b.kinds[s]), int(b.lens[s]), int(b.offs[s])
+        if L == 0:
+            continue
+        alone = sq.fill(k, int(b.keys[s]), int(b.ctr0s[s]), L)
+        assert to_host_bytes(alone).tobytes() == arena[off: off + L * KIND_BYTES[k]].tobytes(), s
+    torch.cuda.synchronize()
+
+
+def test_batch_invalid_descriptors_skipped(sq, oracle_mod):
+    """Streams with an unknown kind, a misaligned offset or a range past the
+    arena are skipped (nothing written) and counted; valid ones are exact."""
+    keys = np.array([11, 12, 13, 14, 15], dtype=np.uint64)
+    ctr0s = np.array([0, 5, 9, 2**64 - 3, 7], dtype=np.uint64)
+    lens = np.array([100, 100, 100, 100, 10**9], dtype=np.uint64)
+    kinds = np.array([0, 9, 2, 3, 1], dtype=np.uint8)
+    offs = np.array([0, 512, 1028, 2048, 4096], dtype=np.uint64)  # stream 2 (u64) misaligned, 4 too long
+    arena = 8192
+    db = sq.batch_to_device(keys, ctr0s, lens, offs, kinds, arena)
+    db.out.fill_(0xCD)
+    sq.fill_batch(db)
+    host = to_host_bytes(db.out)
+    assert sq.batch_errors(db) == 3
+    ref0 = oracle_mod.fill(0, 11, 0, 100).view(np.uint8)
+    ref3 = oracle_mod.fill(3, 14, 2**64 - 3, 100).view(np.uint8)
+    assert host[0:400].tobytes() == ref0.tobytes()
+    assert host[2048:2848].tobytes() == ref3.tobytes()
+    untouched = np.ones(arena, dtype=bool)
+    untouched[0:400] = False
+    untouched[2048:2848] = False
+    assert np.all(host[:arena][untouched] == 0xCD)
+
+
+def test_batch_graph_plan_replays_current_descriptors(sq, oracle_mod):
+    """A captured plan replays with whatever the descriptor arrays hold at
+    launch time; every replay equals the eager batch."""
+    import torch
+
+    from paper_2004_06278_amd import workloads as W
+
+    b1 = W.small_random_batch(seed=21, m=64, max_len=30000, misalign=False)
+    b2 = W.small_random_batch(seed=22, m=64, max_len=30000, misalign=False)
+    size = max(b1.arena_bytes, b2.arena_bytes)
+    db = sq.batch_to_device(b1.keys, b1.ctr0s, b1.lens, b1.offs, b1.kinds, size)
+    plan = sq.BatchPlan(db)
+    for rep, b in enumerate([b1, b2, b1, b2]):
+        log(f"plan replay {rep}")
+        for dst, src in ((db.keys, b.keys), (db.ctr0s, b.ctr0s), (db.lens, b.lens), (db.offs, b.offs)):
+            dst.copy_(torch.from_numpy(np.ascontiguousarray(src).view(np.int64)))
+        db.kinds.copy_(torch.from_numpy(b.kinds))
+        db.out.zero_()
+        torch.cuda.synchronize()
+        plan.launch()
+        torch.cuda.synchronize()
+        got = to_host_bytes(db.out)[: b.arena_bytes]
+        ref = _oracle_arena(oracle_mod, b)
+        assert got.tobytes() == ref.tobytes(), first_diff(got, ref)
+    plan.close()
+
+
+def test_batch_wrap_and_width_stress_full(sq, oracle_mod):
+    """65536 squares64 streams, lengths 1..65536, counters starting within 2^16
+    of 2^64 (about half wrap to 0), U64 and F64 outputs: every output compared."""
+    import torch
+
+    from paper_2004_06278_amd import workloads as W
+
+    b = W.wrap_batch()
+    log(f"wrap stress m={b.m} outputs={b.total_outputs} bytes={b.arena_bytes}")
+    wraps = int(np.sum(b.lens > (np.uint64(0) - b.ctr0s)))
+    assert wraps > b.m // 3
+    db = sq.batch_to_device(b.keys, b.ctr0s, b.lens, b.offs, b.kinds, b.arena_bytes)
+    sq.fill_batch(db)
+    torch.cuda.synchronize()
+    assert sq.batch_errors(db) == 0
+    errors = compare_batch_arena(oracle_mod, db.out, b)
+    assert not errors, errors[:5]
+    del db
+    torch.cuda.empty_cache()
+
+
+def test_batch_ragged_4096_sampled(sq, oracle_mod):
+    """The 4096-key ragged workload (lengths log-uniform in [2^10, 2^24], U32/F32,
+    uniform counters, misaligned starts): the first/last 256 outputs and 256
+    random outputs of every stream equal the oracle's."""
+    import torch
+
+    from paper_2004_06278_amd import workloads as W
+
+    b = W.ragged_batch(misalign=True)
+    log(f"ragged m={b.m} outputs={b.total_outputs} bytes={b.arena_bytes}")
+    db = sq.batch_to_device(b.keys, b.ctr0s, b.lens, b.offs, b.kinds, b.arena_bytes)
+    sq.fill_batch(db)
+    torch.cuda.synchronize()
+    assert sq.batch_errors(db) == 0
+    g = np.random.Generator(np.random.PCG64(77))
+    flat = db.out.view(torch.int32)
+    for s in range(b.m):
+        L, k = int(b.lens[s]), int(b.kinds[s])
+        idx = np.unique(np.concatenate([np.arange(min(L, 256)), L - 1 - np.arange(min(L, 256)),
+                                        g.integers(0, L, size=256)]))
+        base = int(b.offs[s]) // 4
+        got = flat[torch.from_numpy(base + idx.astype(np.int64)).cuda()].cpu().numpy().view(np.uint8)
+        ref = np.concatenate([oracle_mod.fill(k, int(b.keys[s]), (int(b.ctr0s[s]) + int(i)) % 2**64, 1).view(np.uint8)
+                              for i in idx])
+        assert got.tobytes() == ref.tobytes(), s
+    del db, flat
+    torch.cuda.empty_cache()

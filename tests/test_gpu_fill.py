@@ -1,0 +1,149 @@
+"""GPU parity of the bulk fills (squares32/squares64, integer and uniform
+kinds) against the CPU oracle, element by element."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from gpu_helpers import HOST_THREADS, KIND_BYTES, first_diff, log, oracle_bytes, to_host_bytes
+
+pytestmark = pytest.mark.gpu
+
+KINDS = [0, 1, 2, 3]
+
+
+@pytest.fixture(scope="module")
+def sq():
+    import torch
+
+    from paper_2004_06278_amd import squares
+
+    squares.lib()
+    assert torch.cuda.is_available()
+    return squares
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_fill_small_random_misaligned(sq, oracle_mod, kind):
+    """Random keys, counters and lengths 0..5000 at every element-aligned start
+    offset inside a guarded buffer: outputs match the oracle and no byte
+    outside [start, start + n*W) changes."""
+    import torch
+
+    g = np.random.Generator(np.random.PCG64(100 + kind))
+    W = KIND_BYTES[kind]
+    buf = torch.empty(5000 * 8 + 256, dtype=torch.uint8, device="cuda")
+    for trial in range(40):
+        n = int(g.integers(0, 5001)) if trial > 3 else [0, 1, 2, 3][trial]
+        off = W * int(g.integers(0, 16 // W + 2))
+        key = int(g.integers(0, 2**64, dtype=np.uint64))
+        ctr0 = int(g.integers(0, 2**64, dtype=np.uint64)) if trial % 3 else 2**64 - int(g.integers(1, 3000))
+        log(f"fill kind={kind} trial={trial} n={n} off={off} key={key:#x} ctr0={ctr0:#x}")
+        buf.fill_(0xAB)
+        sq.fill_ptr(kind, key, ctr0, n, buf.data_ptr() + 64 + off)
+        torch.cuda.synchronize()
+        host = to_host_bytes(buf)
+        got = host[64 + off: 64 + off + n * W]
+        ref = oracle_bytes(oracle_mod, kind, key, ctr0, n)
+        assert got.tobytes() == ref.tobytes(), first_diff(got, ref)
+        assert np.all(host[: 64 + off] == 0xAB) and np.all(host[64 + off + n * W:] == 0xAB), "write outside range"
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_fill_every_config(sq, oracle_mod, kind):
+    """Every launch configuration the tuner may choose gives identical bits on
+    a ragged size spanning many chunks (and a partial last chunk)."""
+    n = 3 * (1 << 18) + 7
+    key, ctr0 = 0xE3B0C44298FC1C14, 2**64 - 100000
+    ref = oracle_bytes(oracle_mod, kind, key, ctr0, n)
+    for block in (256, 512, 1024):
+        for unroll in (4, 8):
+            for gpc in (1, 4, 16, 64):
+                for xcd in (0, 1):
+                    c = sq.cfg(block, unroll, gpc, xcd)
+                    log(f"fill kind={kind} cfg={c.as_dict()} n={n}")
+                    out = sq.fill(kind, key, ctr0, n, launch_cfg=c)
+                    got = to_host_bytes(out)
+                    assert got.tobytes() == ref.tobytes(), (c.as_dict(), first_diff(got, ref))
+
+
+def test_invalid_arguments(sq):
+    import torch
+
+    buf = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    with pytest.raises(sq.SquaresError) as e:
+        sq.fill_ptr(0, 1, 0, 4, buf.data_ptr() + 2)  # not 4-byte aligned
+    assert e.value.status == -2
+    with pytest.raises(sq.SquaresError) as e:
+        sq.fill_ptr(2, 1, 0, 2, buf.data_ptr() + 4)  # not 8-byte aligned for u64
+    assert e.value.status == -2
+    with pytest.raises(sq.SquaresError) as e:
+        sq.fill_ptr(7, 1, 0, 2, buf.data_ptr())  # unknown kind
+    assert e.value.status == -1
+    with pytest.raises(sq.SquaresError) as e:
+        sq.fill_ptr(0, 1, 0, 2, 0)  # null with n > 0
+    assert e.value.status == -1
+    sq.fill_ptr(0, 1, 0, 0, 0)  # n == 0: no launch, OK
+    with pytest.raises(sq.SquaresError):
+        sq.fill(0, 1, 0, 16, launch_cfg=sq.cfg(block=128))
+
+
+def test_argument_order_matches_paper_scalar(sq, oracle_mod):
+    """The bulk calls take (key, ctr0); the paper's functions take (ctr, key):
+    sq32_fill(key, ctr, 1)[0] == squares32(ctr, key)."""
+    g = np.random.Generator(np.random.PCG64(7))
+    for _ in range(20):
+        ctr = int(g.integers(0, 2**64, dtype=np.uint64))
+        key = int(g.integers(0, 2**64, dtype=np.uint64))
+        a = int(sq.sq32_fill(key, ctr, 1).cpu().numpy()[0])
+        b = int(sq.sq64_fill(key, ctr, 1).cpu().numpy()[0])
+        assert a == oracle_mod.squares32(ctr, key)
+        assert b == oracle_mod.squares64(ctr, key)
+
+
+def test_named_entry_points(sq, oracle_mod):
+    key, ctr0, n = 0x7A3C91E4B85D2F60, 12345, 10007
+    for fn, kind in ((sq.sq32_fill, 0), (sq.uniform_f32, 1), (sq.sq64_fill, 2), (sq.uniform_f64, 3)):
+        out = fn(key, ctr0, n)
+        assert to_host_bytes(out).tobytes() == oracle_bytes(oracle_mod, kind, key, ctr0, n).tobytes()
+
+
+def test_plain_fill_64mib(sq, oracle_mod):
+    """The 64 MiB squares32 fill (one distinct-digit key, counters 0..2^24-1)
+    in full, plus squares64 on the same counters and the hi32 identity."""
+    from paper_2004_06278_amd import workloads as W
+
+    c = W.plain_fill_case()
+    log(f"plain fill key={c.key:#x} n={c.n}")
+    u32 = sq.sq32_fill(c.key, c.ctr0, c.n).cpu().numpy()
+    ref = oracle_mod.fill(0, c.key, c.ctr0, c.n, threads=HOST_THREADS)
+    assert np.array_equal(u32, ref)
+    u64 = sq.sq64_fill(c.key, c.ctr0, c.n).cpu().numpy()
+    assert np.array_equal(u64 >> np.uint64(32), u32.astype(np.uint64))
+    assert np.array_equal(u64, oracle_mod.fill(2, c.key, c.ctr0, c.n, threads=HOST_THREADS))
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_full_size_sampled(sq, oracle_mod, kind):
+    """n = 2^32 outputs from a random 64-bit counter under a distinct-digit key,
+    in the launch configuration the benchmark uses: the first and last 2^16
+    outputs and 2^16 random positions equal the oracle's."""
+    import torch
+
+    from paper_2004_06278_amd import workloads as W
+
+    c = W.single_key_case()
+    n = 1 << 32
+    log(f"full-size fill kind={kind} key={c.key:#x} ctr0={c.ctr0:#x} n={n}")
+    out = sq.fill(kind, c.key, c.ctr0, n)
+    W_ = KIND_BYTES[kind]
+    iv = out.view(torch.int32 if W_ == 4 else torch.int64)
+    g = np.random.Generator(np.random.PCG64(55 + kind))
+    idx = np.unique(np.concatenate([np.arange(1 << 16), n - 1 - np.arange(1 << 16),
+                                    g.integers(0, n, size=1 << 16)]))
+    got = iv[torch.from_numpy(idx.astype(np.int64)).cuda()].cpu().numpy().view(np.uint8).reshape(-1, W_)
+    for row, i in zip(got, idx):
+        ref = oracle_mod.fill(kind, c.key, (c.ctr0 + int(i)) % 2**64, 1).view(np.uint8)
+        assert row.tobytes() == ref.tobytes(), f"position {int(i)}"
+    del out, iv
+    torch.cuda.empty_cache()

@@ -1,0 +1,98 @@
+"""GPU parity of the fused exact reduce against the oracle's exact sum and its
+round-to-nearest-even double."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from gpu_helpers import HOST_THREADS, log
+
+pytestmark = pytest.mark.gpu
+
+KINDS = [0, 1, 2, 3]
+
+
+@pytest.fixture(scope="module")
+def sq():
+    from paper_2004_06278_amd import squares
+
+    squares.lib()
+    return squares
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_reduce_small_and_ragged(sq, oracle_mod, kind):
+    g = np.random.Generator(np.random.PCG64(200 + kind))
+    sizes = [0, 1, 2, 3, 63, 64, 65, 255, 256, 257, 1000, 65536 + 3, 1 << 20, (1 << 22) + 11]
+    for n in sizes:
+        key = int(g.integers(0, 2**64, dtype=np.uint64))
+        ctr0 = 2**64 - int(g.integers(1, 1 << 21)) if n % 2 else int(g.integers(0, 2**64, dtype=np.uint64))
+        log(f"reduce kind={kind} n={n} key={key:#x} ctr0={ctr0:#x}")
+        s, v, nn = sq.reduce(kind, key, ctr0, n)
+        ref = oracle_mod.exact_sum(kind, key, ctr0, n, threads=HOST_THREADS)
+        assert s == ref, (n, s, ref)
+        assert v == oracle_mod.rounded_value(kind, ref)
+        assert nn == n
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_reduce_every_config(sq, oracle_mod, kind):
+    n = (1 << 21) + 77
+    key, ctr0 = 0x51A8F3C2E9D07B64, 2**64 - 12345
+    ref = oracle_mod.exact_sum(kind, key, ctr0, n, threads=HOST_THREADS)
+    for unroll in (1, 2, 4):
+        for gpc in (1, 2, 8, 32, 64):
+            c = sq.cfg(256, unroll, gpc)
+            log(f"reduce kind={kind} cfg={c.as_dict()}")
+            s, v, _ = sq.reduce(kind, key, ctr0, n, launch_cfg=c)
+            assert s == ref, c.as_dict()
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_reduce_additive(sq, kind):
+    """reduce[a, b) + reduce[b, c) == reduce[a, c), across the counter wrap."""
+    key, a = 0x0F1E2D3C4B5A6978, 2**64 - 3_000_000
+    whole, _, _ = sq.reduce(kind, key, a, 10_000_000)
+    for b in (1, 2_999_999, 3_000_000, 7_777_777):
+        l, _, _ = sq.reduce(kind, key, a, b)
+        r, _, _ = sq.reduce(kind, key, (a + b) % 2**64, 10_000_000 - b)
+        assert l + r == whole
+
+
+@pytest.mark.parametrize("kind", [1, 3])
+def test_reduce_full_size_exact(sq, oracle_mod, kind):
+    """The fused F32 / F64 consumers over n = 2^32 outputs from a random
+    counter (the single-key workload), compared with the oracle's exact sum
+    computed on all host threads."""
+    from paper_2004_06278_amd import workloads as W
+
+    c = W.single_key_case()
+    n = 1 << 32
+    log(f"full-size reduce kind={kind} key={c.key:#x} ctr0={c.ctr0:#x}")
+    s, v, _ = sq.reduce(kind, c.key, c.ctr0, n)
+    ref = oracle_mod.exact_sum(kind, c.key, c.ctr0, n, threads=HOST_THREADS)
+    assert s == ref
+    assert v == oracle_mod.rounded_value(kind, ref)
+    # mean of uniforms on [0,1) over 2^32 draws
+    assert abs(v / n - 0.5) < 1e-4
+
+
+def test_reduce_u64_carries(sq, oracle_mod):
+    """A U64 sum over 2^24 outputs exceeds 2^64: the high word must carry."""
+    key, ctr0, n = 0xC3A5C85C97CB3127, 99, 1 << 24
+    s, v, _ = sq.reduce(2, key, ctr0, n)
+    assert s == oracle_mod.exact_sum(2, key, ctr0, n, threads=HOST_THREADS)
+    assert s > 2**64
+
+
+def test_reduce_rejects_bad_workspace(sq):
+    import torch
+
+    res = sq.result_tensor()
+    small = torch.empty(64, dtype=torch.uint8, device="cuda")
+    with pytest.raises(sq.SquaresError) as e:
+        sq.reduce_async(0, 1, 0, 100, res, small)
+    assert e.value.status == -3
+    with pytest.raises(sq.SquaresError) as e:
+        sq.reduce_async(9, 1, 0, 100, res, sq.reduce_workspace())
+    assert e.value.status == -1
