@@ -1,0 +1,267 @@
+#!/usr/bin/env python3
+"""Benchmark of the Squares RNG hot path on one MI355X.
+
+Workload (single-key throughput): one distinct-digit key, a uniformly random
+64-bit starting counter, n = 2^32 outputs per operation.  One step is
+    squares32 fill to HBM     (16 GiB of uint32)
+    squares64 fill to HBM     (32 GiB of uint64)
+    fused f32 sum             (squares32 -> 24-bit uniform, summed exactly in registers, no per-element writes)
+    fused f64 sum             (squares64 -> 53-bit uniform, summed exactly in registers)
+so a step produces 4 * 2^32 numbers.  The timed region holds exactly --steps
+steps with a device synchronisation on both sides; inputs are scalars, so
+nothing is transferred.  The JSON line carries the whole-step rate, each
+kernel's average duration from HIP events on the launch stream, the
+roofline of the dominant kernel, the CPU oracle's rate on a bounded sample,
+and (unless --no-extras) the ragged-batch speedup over per-stream launches
+and serving latency percentiles.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--log2n 32] [--no-extras]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, published
+CUS, CLOCK_HZ = 256, 2.4e9      # MI355X compute units and peak engine clock
+# Full-rate VALU issue of the 64-bit / multiply class (v_mad_u64_u32,
+# v_mul_lo_u32, v_lshl_add_u64, fp64 FMA): 64 lanes per CU per clock
+# (fp64 vector 78.6 TFLOP/s = 256 CUs * 2.4 GHz * 64 lanes * 2 flops).
+# 32-bit adds/shifts/logic issue at twice that rate and count half a slot.
+ALU_PEAK_SLOTS = CUS * CLOCK_HZ * 64
+# Algorithmic VALU work per output in such slots: a round is one 32x32->64
+# multiply-add (1) + one 32-bit multiply (1) + one 32-bit shift-add (0.5); the
+# Weyl step to the next counter is one 64-bit add (1).
+SLOTS = {
+    "sq32": 4 * 2.5 + 1.0,                 # 11
+    "sq64": 5 * 2.5 + 0.5 + 1.0,           # 14 (+ the xor of round 5)
+    "sum_f32": 0.5 + 1.0,                  # >> 8, 64-bit accumulate
+    "sum_f64": 1.0 + 1.0,                  # 64-bit >> 11, 64-bit accumulate
+}
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--log2n", type=int, default=32)
+    p.add_argument("--no-extras", action="store_true")
+    p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--calib-copy", action="store_true",
+                   help="run a plain 4 GiB device copy first (scales HBM byte counters)")
+    return p.parse_args()
+
+
+def cpu_baseline(key: int, ctr0: int, log2_sample: int = 30) -> dict:
+    """The oracle as it stands, on the host cores, over the same four
+    operations for 2^log2_sample counters each (same key and start).  The
+    fills write into a reused host buffer of 2^26 elements, one chunk at a
+    time; the sums write nothing."""
+    import numpy as np
+
+    from oracle import oracle
+
+    threads = max(1, min(16, os.cpu_count() or 1))
+    n = 1 << log2_sample
+    chunk = min(n, 1 << 26)
+    u32 = np.zeros(chunk, dtype=np.uint32)
+    u64 = np.zeros(chunk, dtype=np.uint64)
+    t0 = time.perf_counter()
+    for base in range(0, n, chunk):
+        oracle.fill_into(oracle.U32, key, (ctr0 + base) % 2**64, u32, threads=threads)
+    for base in range(0, n, chunk):
+        oracle.fill_into(oracle.U64, key, (ctr0 + base) % 2**64, u64, threads=threads)
+    oracle.exact_sum(oracle.F32, key, ctr0, n, threads=threads)
+    oracle.exact_sum(oracle.F64, key, ctr0, n, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": round(4 * n / dt / 1e9, 3), "unit": "Gnum/s", "cores": threads, "kind": "oracle",
+            "sample": f"2^{log2_sample} counters of each of the 4 step operations (same key and ctr0; fills "
+                      f"into a reused 2^26-element host buffer), {threads} host threads, {dt:.2f} s wall"}
+
+
+def batch_speedup(sq, torch) -> dict:
+    """4096 keys, log-uniform lengths in [2^10, 2^24], U32/F32: one replay of the
+    captured batch plan vs 4096 separate fill launches on one stream."""
+    from paper_2004_06278_amd import workloads as W
+
+    b = W.ragged_batch(seed=3)
+    db = sq.batch_to_device(b.keys, b.ctr0s, b.lens, b.offs, b.kinds, b.arena_bytes)
+    plan = sq.BatchPlan(db)
+
+    def per_stream():
+        sq.fill_streams(b.keys, b.ctr0s, b.lens, b.offs, b.kinds, db.out, b.arena_bytes)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        best = 1e30
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        return best
+
+    t_plan = timed(plan.launch, 5)
+    t_each = timed(per_stream, 3)
+    plan.close()
+    n = b.total_outputs
+    del db
+    torch.cuda.empty_cache()
+    return {"workload": "4096 keys, log-uniform lengths 2^10..2^24, U32/F32", "outputs": n,
+            "graph_ms": round(t_plan * 1e3, 3), "per_stream_ms": round(t_each * 1e3, 3),
+            "graph_gnum_s": round(n / t_plan / 1e9, 1), "per_stream_gnum_s": round(n / t_each / 1e9, 1),
+            "speedup": round(t_each / t_plan, 2)}
+
+
+def main() -> int:
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1).", file=sys.stderr)
+        return 2
+    import torch
+
+    from paper_2004_06278_amd import squares as sq
+    from paper_2004_06278_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    sq.check(sq.lib().sq_init())
+    case = W.single_key_case()
+    key, ctr0, n = case.key, case.ctr0, 1 << args.log2n
+
+    if args.calib_copy:
+        src = torch.empty(4 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        torch.cuda.empty_cache()
+
+    out32 = torch.empty(n, dtype=torch.uint32, device="cuda")
+    out64 = torch.empty(n, dtype=torch.uint64, device="cuda")
+    res32, res64 = sq.result_tensor(), sq.result_tensor()
+    ws32, ws64 = sq.reduce_workspace(n), sq.reduce_workspace(n)
+    ops = [
+        ("sq32_fill", lambda: sq.fill(sq.U32, key, ctr0, n, out=out32)),
+        ("sq64_fill", lambda: sq.fill(sq.U64, key, ctr0, n, out=out64)),
+        ("fused_f32_sum", lambda: sq.reduce_async(sq.F32, key, ctr0, n, res32, ws32)),
+        ("fused_f64_sum", lambda: sq.reduce_async(sq.F64, key, ctr0, n, res64, ws64)),
+    ]
+    ev = {name: [] for name, _ in ops}
+
+    def step(record: bool):
+        for name, fn in ops:
+            if record:
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                fn()
+                b.record()
+                ev[name].append((a, b))
+            else:
+                fn()
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    per_op_ms = {name: sum(a.elapsed_time(b) for a, b in ev[name]) / len(ev[name]) for name in ev}
+    value = 4 * n / (ms_per_step * 1e-3) / 1e9
+
+    # spot check of the timed outputs against the oracle (outside the timed region)
+    from oracle import oracle
+    import numpy as np
+
+    idx = torch.tensor([0, 1, n // 3, n - 1], dtype=torch.int64, device="cuda")
+    got32 = out32.view(torch.int32)[idx].cpu().numpy().view(np.uint32)
+    got64 = out64.view(torch.int64)[idx].cpu().numpy().view(np.uint64)
+    for i, g32, g64 in zip(idx.cpu().tolist(), got32, got64):
+        assert int(g32) == oracle.squares32((ctr0 + i) % 2**64, key), "sq32 spot check failed"
+        assert int(g64) == oracle.squares64((ctr0 + i) % 2**64, key), "sq64 spot check failed"
+    s32, v32, _ = sq.read_result(res32)
+    s64, v64, _ = sq.read_result(res64)
+    assert abs(v32 / n - 0.5) < 1e-3 and abs(v64 / n - 0.5) < 1e-3
+
+    def hbm_roof(name, nbytes):
+        ms = per_op_ms[name]
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": name, "avg_ms": round(ms, 4), "algorithmic_bytes": nbytes}
+
+    def alu_roof(name, slots):
+        ms = per_op_ms[name]
+        rate = slots * n / (ms * 1e-3)
+        return {"bound": "alu", "achieved": round(rate / 1e12, 3), "peak": round(ALU_PEAK_SLOTS / 1e12, 3),
+                "unit": "T VALU-slot/s", "frac": round(rate / ALU_PEAK_SLOTS, 4), "traffic": None,
+                "kernel": name, "avg_ms": round(ms, 4), "slots_per_output": slots}
+
+    rooflines = {
+        "sq32_fill": hbm_roof("sq32_fill", 4 * n),
+        "sq64_fill": hbm_roof("sq64_fill", 8 * n),
+        "fused_f32_sum": alu_roof("fused_f32_sum", SLOTS["sq32"] + SLOTS["sum_f32"]),
+        "fused_f64_sum": alu_roof("fused_f64_sum", SLOTS["sq64"] + SLOTS["sum_f64"]),
+    }
+    dominant = max(per_op_ms, key=per_op_ms.get)
+    traffic_file = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(traffic_file):
+        with open(traffic_file) as f:
+            tr = json.load(f)
+        for k, r in rooflines.items():
+            if k in tr.get("kernels", {}) and args.log2n == tr.get("log2n"):
+                r["traffic"] = tr["kernels"][k]
+
+    line = {
+        "metric": "Gnum/s squares32/64 (fill vs fused) and % HBM/VALU roofline; batch speedup; p99",
+        "value": round(value, 2),
+        "unit": "Gnum/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": f"single-key throughput: squares32+squares64 fill to HBM and fused "
+                               f"f32/f64 exact sums, n=2^{args.log2n} each, one distinct-digit key, "
+                               f"random 64-bit ctr0", "n": n, "key": hex(key), "ctr0": hex(ctr0),
+                   "parallelism": "single GPU"},
+        "per_kernel_gnum_s": {k: round(n / (v * 1e-3) / 1e9, 1) for k, v in per_op_ms.items()},
+        "per_kernel_ms": {k: round(v, 4) for k, v in per_op_ms.items()},
+        "roofline": rooflines[dominant],
+        "rooflines": rooflines,
+    }
+    del out32, out64
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        line["batch"] = batch_speedup(sq, torch)
+        try:
+            from paper_2004_06278_amd import serve_bench
+
+            line["serving"] = serve_bench.run_short(sq, torch)
+        except ImportError:
+            pass
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(key, ctr0)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

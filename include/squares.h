@@ -168,6 +168,14 @@ int sq_fill_batch_cfg(const uint64_t *keys, const uint64_t *ctr0s, const uint64_
                       const uint64_t *offs, const uint8_t *kinds, uint32_t m, void *out,
                       uint64_t out_bytes, void *ws, size_t ws_bytes, const sq_launch_cfg *cfg,
                       void *stream);
+/* The same streams as separate launches: one sq_fill kernel per stream,
+ * enqueued in order on `stream`.  Here the five descriptor arrays are HOST
+ * arrays (checked on the host: SQ_EINVAL / SQ_EALIGN before anything is
+ * launched); `out` is the device arena.  This is the per-stream way of
+ * producing a batch, kept for comparison with sq_fill_batch. */
+int sq_fill_streams(const uint64_t *keys, const uint64_t *ctr0s, const uint64_t *lens,
+                    const uint64_t *offs, const uint8_t *kinds, uint32_t m, void *out,
+                    uint64_t out_bytes, void *stream);
 /* Number of skipped streams of the last batch that used `ws` (synchronises
  * `stream`). */
 int sq_batch_errors(const void *ws, void *stream, uint32_t *count);

@@ -188,6 +188,28 @@ int sq_fill_batch(const uint64_t* keys, const uint64_t* ctr0s, const uint64_t* l
   return sq_fill_batch_cfg(keys, ctr0s, lens, offs, kinds, m, out, out_bytes, ws, ws_bytes, &cfg, stream);
 }
 
+int sq_fill_streams(const uint64_t* keys, const uint64_t* ctr0s, const uint64_t* lens, const uint64_t* offs,
+                    const uint8_t* kinds, uint32_t m, void* out, uint64_t out_bytes, void* stream) {
+  if (m == 0) return SQ_OK;
+  if (!keys || !ctr0s || !lens || !offs || !kinds || !out) return fail(SQ_EINVAL, "null host descriptor or arena");
+  SQ_INIT_OR_RETURN();
+  for (uint32_t s = 0; s < m; ++s) {
+    const int W = kind_bytes(kinds[s]);
+    if (W == 0) return fail(SQ_EINVAL, "stream " + std::to_string(s) + ": unknown kind");
+    if (offs[s] % W != 0) return fail(SQ_EALIGN, "stream " + std::to_string(s) + ": misaligned offset");
+    if (offs[s] > out_bytes || lens[s] > (out_bytes - offs[s]) / W)
+      return fail(SQ_EINVAL, "stream " + std::to_string(s) + ": range past the arena");
+  }
+  for (uint32_t s = 0; s < m; ++s) {
+    if (lens[s] == 0) continue;
+    const sq_launch_cfg cfg = tuned_cfg(SQ_OP_FILL, kinds[s], lens[s]);
+    hipError_t e = launch_fill(kinds[s], keys[s], ctr0s[s], lens[s], (unsigned char*)out + offs[s], cfg,
+                               (hipStream_t)stream);
+    if (e != hipSuccess) return fail_hip(e, "fill launch");
+  }
+  return SQ_OK;
+}
+
 int sq_batch_errors(const void* ws, void* stream, uint32_t* count) {
   if (ws == nullptr || count == nullptr) return fail(SQ_EINVAL, "null workspace or count pointer");
   SQ_INIT_OR_RETURN();

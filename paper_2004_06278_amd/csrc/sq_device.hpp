@@ -25,6 +25,15 @@ namespace sqd {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
+// Returns v unchanged, but opaque to the optimizer.  y advances by key per
+// counter, so without this LLVM treats round 1's y*y + y as a polynomial in
+// the loop counter and strength-reduces it into extra multiply-adds.  The
+// empty asm emits no instruction.
+__device__ __forceinline__ uint64_t opaque(uint64_t v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 // rot32(x*x + a)
 __device__ __forceinline__ uint64_t round_rot(uint64_t x, uint64_t a) {
   const uint32_t xl = (uint32_t)x, xh = (uint32_t)(x >> 32);
@@ -50,7 +59,7 @@ __device__ __forceinline__ uint32_t round_hi(uint64_t x, uint64_t a) {
 
 // squares32 from its Weyl terms y = ctr*key, z = (ctr+1)*key.
 __device__ __forceinline__ uint32_t sq32(uint64_t y, uint64_t z) {
-  uint64_t x = round_rot(y, y);  // round 1 (x starts as y)
+  uint64_t x = round_rot(opaque(y), y);  // round 1 (x starts as y)
   x = round_rot(x, z);           // round 2
   x = round_rot(x, y);           // round 3
   return round_hi(x, z);         // round 4: upper half of x*x + z
@@ -59,7 +68,7 @@ __device__ __forceinline__ uint32_t sq32(uint64_t y, uint64_t z) {
 // squares64: round 4 keeps t = x*x + z whole; round 5 squares rot32(t), adds
 // y and its upper 32 bits are XORed into the low word of t.
 __device__ __forceinline__ uint64_t sq64(uint64_t y, uint64_t z) {
-  uint64_t x = round_rot(y, y);
+  uint64_t x = round_rot(opaque(y), y);
   x = round_rot(x, z);
   x = round_rot(x, y);
   uint32_t tl, th;

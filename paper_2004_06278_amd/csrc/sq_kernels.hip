@@ -10,6 +10,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+#include <map>
+#include <mutex>
+
 #include "sq_device.hpp"
 #include "sq_internal.hpp"
 
@@ -408,10 +412,33 @@ hipError_t launch_fill(int kind, uint64_t key, uint64_t ctr0, uint64_t n, void* 
   return hipGetLastError();
 }
 
+// Workgroups of `k` (with `block` threads) that fit on one CU at once.
+static int resident_blocks(const void* k, uint32_t block) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, uint32_t>, int> cache;
+  std::lock_guard<std::mutex> g(mu);
+  auto it = cache.find({k, block});
+  if (it != cache.end()) return it->second;
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, (int)block, 0) != hipSuccess || nb < 1) nb = 1;
+  cache[{k, block}] = nb;
+  return nb;
+}
+
 hipError_t launch_reduce(int kind, uint64_t key, uint64_t ctr0, uint64_t n, sq_sum_result* out, void* ws,
                          const sq_launch_cfg& cfg, hipStream_t s) {
   const uint32_t B = 256;  // reduce workgroups are 256 threads (block_sum128 LDS sized for <= 1024)
-  uint64_t grid = (uint64_t)device_info().cus * cfg.grid_per_cu;
+  ReduceKernel k = nullptr;
+  switch (kind) {
+    case SQ_U32: k = reduce_kernel_for<0>(cfg.unroll); break;
+    case SQ_F32: k = reduce_kernel_for<1>(cfg.unroll); break;
+    case SQ_U64: k = reduce_kernel_for<2>(cfg.unroll); break;
+    default: k = reduce_kernel_for<3>(cfg.unroll); break;
+  }
+  // Every thread gets the same amount of work, so the grid must be resident
+  // at once: a second partial wave of workgroups would double the time.
+  const uint32_t gpc = std::min<uint32_t>(cfg.grid_per_cu, (uint32_t)resident_blocks((const void*)k, B));
+  uint64_t grid = (uint64_t)device_info().cus * gpc;
   const uint64_t need = (n + B - 1) / B;  // at least one output per thread
   if (grid > need) grid = need;
   if (grid == 0) grid = 1;
@@ -423,13 +450,6 @@ hipError_t launch_reduce(int kind, uint64_t key, uint64_t ctr0, uint64_t n, sq_s
   a.n = n;
   a.per = n / T + (n % T != 0);
   a.partials = (uint64_t*)ws;
-  ReduceKernel k = nullptr;
-  switch (kind) {
-    case SQ_U32: k = reduce_kernel_for<0>(cfg.unroll); break;
-    case SQ_F32: k = reduce_kernel_for<1>(cfg.unroll); break;
-    case SQ_U64: k = reduce_kernel_for<2>(cfg.unroll); break;
-    default: k = reduce_kernel_for<3>(cfg.unroll); break;
-  }
   hipLaunchKernelGGL(k, dim3((uint32_t)grid), dim3(B), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -86,6 +86,7 @@ SIGNATURES = {
     "sq_fill_batch": (_int, [_vp, _vp, _vp, _vp, _vp, _u32, _vp, _u64, _vp, ctypes.c_size_t, _vp]),
     "sq_fill_batch_cfg": (_int, [_vp, _vp, _vp, _vp, _vp, _u32, _vp, _u64, _vp, ctypes.c_size_t,
                                  ctypes.POINTER(LaunchCfg), _vp]),
+    "sq_fill_streams": (_int, [_vp, _vp, _vp, _vp, _vp, _u32, _vp, _u64, _vp]),
     "sq_batch_errors": (_int, [_vp, _vp, ctypes.POINTER(_u32)]),
     "sq_batch_plan_create": (_int, [_vp, _vp, _vp, _vp, _vp, _u32, _vp, _u64, _vp, ctypes.c_size_t,
                                     ctypes.POINTER(LaunchCfg), ctypes.POINTER(_vp)]),
@@ -290,6 +291,17 @@ def fill_batch(b: DeviceBatch, stream=None, launch_cfg: LaunchCfg | None = None)
         check(lib().sq_fill_batch(*args, _stream(stream)))
     else:
         check(lib().sq_fill_batch_cfg(*args, ctypes.byref(launch_cfg), _stream(stream)))
+
+
+def fill_streams(keys, ctr0s, lens, offs, kinds, out, out_bytes: int, stream=None) -> None:
+    """One fill launch per stream from HOST descriptor arrays (numpy)."""
+    import numpy as np
+
+    arrs = [np.ascontiguousarray(a, dtype=np.uint64) for a in (keys, ctr0s, lens, offs)]
+    kd = np.ascontiguousarray(kinds, dtype=np.uint8)
+    m = kd.size
+    check(lib().sq_fill_streams(*(a.ctypes.data for a in arrs), kd.ctypes.data, m, _ptr(out), out_bytes,
+                                _stream(stream)))
 
 
 def batch_errors(b: DeviceBatch, stream=None) -> int:
