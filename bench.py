@@ -31,20 +31,67 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, published
 CUS, CLOCK_HZ = 256, 2.4e9      # MI355X compute units and peak engine clock
-# Full-rate VALU issue of the 64-bit / multiply class (v_mad_u64_u32,
-# v_mul_lo_u32, v_lshl_add_u64, fp64 FMA): 64 lanes per CU per clock
-# (fp64 vector 78.6 TFLOP/s = 256 CUs * 2.4 GHz * 64 lanes * 2 flops).
-# 32-bit adds/shifts/logic issue at twice that rate and count half a slot.
+# VALU issue model (measured on this part with paper_2004_06278_amd/calib):
+# v_mad_u64_u32, v_mul_lo_u32, v_lshl_add_u32 and 64-bit adds issue at the
+# full 64 lanes per CU per clock (one "slot"); two-operand 32-bit ops
+# (add, shift, xor) issue up to twice as fast and count half a slot.
+# Peak = 256 CUs * 2.4 GHz * 64 lanes (matching fp64 vector 78.6 TFLOP/s).
 ALU_PEAK_SLOTS = CUS * CLOCK_HZ * 64
-# Algorithmic VALU work per output in such slots: a round is one 32x32->64
-# multiply-add (1) + one 32-bit multiply (1) + one 32-bit shift-add (0.5); the
-# Weyl step to the next counter is one 64-bit add (1).
+# Algorithmic VALU work per output in slots: a round is one 32x32->64
+# multiply-add (1) + one 32-bit multiply (1) + one shift-add (1); the Weyl
+# step to the next counter is one 64-bit add (1).
 SLOTS = {
-    "sq32": 4 * 2.5 + 1.0,                 # 11
-    "sq64": 5 * 2.5 + 0.5 + 1.0,           # 14 (+ the xor of round 5)
+    "sq32": 4 * 3.0 + 1.0,                 # 13
+    "sq64": 5 * 3.0 + 0.5 + 1.0,           # 16.5 (+ the xor of round 5)
     "sum_f32": 0.5 + 1.0,                  # >> 8, 64-bit accumulate
     "sum_f64": 1.0 + 1.0,                  # 64-bit >> 11, 64-bit accumulate
 }
+KERNEL_SOURCES = ["paper_2004_06278_amd/csrc/sq_device.hpp", "paper_2004_06278_amd/csrc/sq_kernels.hip"]
+# rocprofv3 kernel-name prefixes of the four step operations
+KERNEL_NAMES = {"sq32_fill": "k_fill<0,", "sq64_fill": "k_fill<2,", "fused_f32_sum": "k_reduce<1,",
+                "fused_f64_sum": "k_reduce<3,"}
+
+
+def kernel_source_sha() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_pmc(fetch_csv: str, write_csv: str, log2n: int) -> dict:
+    """HBM bytes per launch of each step kernel from two rocprofv3 --pmc runs
+    (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by what the same
+    counter reads for the plain 4 GiB device copy that --calib-copy runs
+    first (the largest __amd_rocclr_copyBuffer dispatch)."""
+    import csv
+
+    def load(path):
+        rows = list(csv.DictReader(open(path)))
+        copy = max((r for r in rows if "copyBuffer" in r["Kernel_Name"]), key=lambda r: float(r["Counter_Value"]))
+        per = {}
+        for name, pref in KERNEL_NAMES.items():
+            vals = [float(r["Counter_Value"]) * 1024 for r in rows
+                    if pref in r["Kernel_Name"].replace(" ", "").replace("(anonymousnamespace)::", "")]
+            per[name] = sum(vals) / len(vals) if vals else None
+        return float(copy["Counter_Value"]) * 1024, per
+
+    copy_f, fetch = load(fetch_csv)
+    copy_w, write = load(write_csv)
+    ref = float(4 << 30)
+    ff, fw = ref / copy_f, ref / copy_w
+    kernels, detail = {}, {}
+    for name in KERNEL_NAMES:
+        if fetch[name] is None or write[name] is None:
+            continue
+        kernels[name] = round(fetch[name] * ff + write[name] * fw)
+        detail[name] = {"fetch_bytes": round(fetch[name] * ff), "write_bytes": round(write[name] * fw)}
+    return {"source_sha": kernel_source_sha(), "log2n": log2n,
+            "factors": {"fetch": round(ff, 4), "write": round(fw, 4), "copy_bytes": int(ref)},
+            "kernels": kernels, "detail": detail}
 
 
 def parse():
@@ -57,6 +104,8 @@ def parse():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--calib-copy", action="store_true",
                    help="run a plain 4 GiB device copy first (scales HBM byte counters)")
+    p.add_argument("--traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                   help="write profiles/traffic.json from two rocprofv3 --pmc counter_collection.csv files")
     return p.parse_args()
 
 
@@ -124,6 +173,12 @@ def batch_speedup(sq, torch) -> dict:
 
 def main() -> int:
     args = parse()
+    if args.traffic:
+        t = traffic_from_pmc(args.traffic[0], args.traffic[1], args.log2n)
+        with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
+            json.dump(t, f, indent=1)
+        print(json.dumps(t))
+        return 0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1).", file=sys.stderr)
@@ -221,9 +276,11 @@ def main() -> int:
     if os.path.exists(traffic_file):
         with open(traffic_file) as f:
             tr = json.load(f)
-        for k, r in rooflines.items():
-            if k in tr.get("kernels", {}) and args.log2n == tr.get("log2n"):
-                r["traffic"] = tr["kernels"][k]
+        # counters taken on other kernel sources or another size do not apply
+        if tr.get("source_sha") == kernel_source_sha() and tr.get("log2n") == args.log2n:
+            for k, r in rooflines.items():
+                if k in tr.get("kernels", {}):
+                    r["traffic"] = tr["kernels"][k]
 
     line = {
         "metric": "Gnum/s squares32/64 (fill vs fused) and % HBM/VALU roofline; batch speedup; p99",

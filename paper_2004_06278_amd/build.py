@@ -49,5 +49,21 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_calib(verbose: bool = False) -> str:
+    """Builds the calibration program (VALU issue rates, HBM store ceiling)."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    src = os.path.join(HERE, "calib", "sq_calib.hip")
+    exe = os.path.join(HERE, "calib", "sq_calib")
+    cmd = [hipcc, *FLAGS, src, "-o", exe]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("hipcc failed on sq_calib.hip")
+    return exe
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_calib(verbose=True))

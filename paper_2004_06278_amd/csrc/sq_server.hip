@@ -1,0 +1,513 @@
+// Continuous-batching request server.
+//
+// The generators are stateless (a request is fully described by kind, key,
+// starting counter and length), so the whole state of an admitted request
+// is one 48-byte slot: key, ctr0, n, output offset, progress, kind.  Slots
+// live in a device table; admissions upload them on a control stream.
+//
+// A scheduler thread loops:
+//   1. retire ticks whose completion event has fired; a request completes
+//      when all of its outputs were scheduled and no tick holding one of its
+//      chunks is still running;
+//   2. admit queued requests in arrival order while a slot is free and the
+//      output arena (hbm_budget_bytes, owned by the server) has room;
+//   3. if a tick stream is idle and some admitted request has outputs left,
+//      build a tick: the next chunk (at most chunk_cap outputs) of every such
+//      request, written into that stream's pinned tick buffer, which the
+//      tick's first kernel reads directly; then replay the stream's captured
+//      graph (expand -> tile scan -> persistent fill) after waiting for the
+//      control stream's latest slot upload.
+// Up to n_streams ticks are in flight at once, so requests admitted while
+// others run share the device with them.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <unordered_set>
+#include <vector>
+
+#include "sq_internal.hpp"
+
+using namespace sqi;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+double now_s() { return std::chrono::duration<double>(Clock::now().time_since_epoch()).count(); }
+
+enum class St { Queued, Active, Done };
+
+struct Req {
+  uint64_t id;
+  int kind;
+  uint64_t key, ctr0, n;
+  uint32_t flags;
+  St st = St::Queued;
+  uint64_t off = 0, bytes = 0;  // arena range
+  uint32_t slot = 0;
+  uint64_t next = 0;            // next output to schedule
+  uint32_t inflight = 0;        // running ticks that hold a chunk of this request
+  double t_submit = 0, t_done = 0;
+};
+
+// First-fit allocator over [0, size) in 256-byte units.
+class Arena {
+ public:
+  explicit Arena(uint64_t size) { free_[0] = size; }
+  bool alloc(uint64_t bytes, uint64_t* off) {
+    bytes = (bytes + 255) & ~255ull;
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        *off = it->first;
+        const uint64_t rest = it->second - bytes, at = it->first + bytes;
+        free_.erase(it);
+        if (rest) free_[at] = rest;
+        used_ += bytes;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(uint64_t off, uint64_t bytes) {
+    bytes = (bytes + 255) & ~255ull;
+    used_ -= bytes;
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  uint64_t used() const { return used_; }
+
+ private:
+  std::map<uint64_t, uint64_t> free_;
+  uint64_t used_ = 0;
+};
+
+struct TickLane {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  unsigned char* host_buf = nullptr;  // pinned: TickHdr + entries, read by the device
+  void* ws = nullptr;                 // device tick workspace
+  bool busy = false;
+  std::vector<uint64_t> reqs;         // requests with a chunk in the running tick
+};
+
+}  // namespace
+
+struct sq_server {
+  sq_server_cfg cfg{};
+  sq_launch_cfg lcfg{};
+  int device = 0;
+  unsigned char* arena_dev = nullptr;
+  SlotDev* slots_dev = nullptr;
+  SlotDev* slots_stage = nullptr;     // pinned, one record per slot
+  hipStream_t ctl = nullptr;
+  hipEvent_t ctl_ev = nullptr;
+  std::vector<TickLane> lanes;
+
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<uint64_t> queue;
+  std::unordered_map<uint64_t, Req> reqs;
+  std::vector<uint64_t> active;       // admitted, not complete, in admission order
+  std::vector<uint32_t> free_slots;
+  std::unordered_set<uint64_t> cancelled;
+  Arena* arena = nullptr;
+  uint64_t next_id = 1;
+  bool stop = false;
+  std::string fatal;                  // first HIP error seen by the scheduler
+  std::thread th;
+
+  std::vector<double> lat;            // latencies of completed requests
+  uint64_t submitted = 0, admitted = 0, completed = 0, released = 0, outputs = 0, bytes_done = 0, ticks = 0;
+  double first_submit = 0, last_complete = 0;
+
+  void loop();
+  bool retire_locked();
+  bool admit_locked(std::vector<uint32_t>* new_slots);
+  bool tick_locked(const std::vector<uint32_t>& new_slots);
+  void finish_locked(Req& r);
+};
+
+void sq_server::finish_locked(Req& r) {
+  r.st = St::Done;
+  r.t_done = now_s();
+  lat.push_back(r.t_done - r.t_submit);
+  ++completed;
+  outputs += r.n;
+  bytes_done += r.bytes;
+  last_complete = r.t_done;
+  free_slots.push_back(r.slot);
+  active.erase(std::find(active.begin(), active.end(), r.id));
+  if (r.flags & SQ_SERVE_DISCARD) {
+    arena->release(r.off, r.bytes);
+    ++released;
+    const uint64_t id = r.id;  // r dies with the erase
+    reqs.erase(id);
+  }
+  cv_done.notify_all();
+}
+
+// Retires finished ticks; returns true if any retired.
+bool sq_server::retire_locked() {
+  bool any = false;
+  for (auto& L : lanes) {
+    if (!L.busy) continue;
+    hipError_t q = hipEventQuery(L.done);
+    if (q == hipErrorNotReady) continue;
+    if (q != hipSuccess && fatal.empty()) fatal = std::string("tick: ") + hipGetErrorString(q);
+    L.busy = false;
+    any = true;
+    for (uint64_t id : L.reqs) {
+      Req& r = reqs.at(id);
+      if (--r.inflight == 0 && r.next == r.n) finish_locked(r);
+    }
+    L.reqs.clear();
+  }
+  return any;
+}
+
+// Admits queued requests (FIFO) while a slot and arena room exist.
+bool sq_server::admit_locked(std::vector<uint32_t>* new_slots) {
+  bool any = false;
+  while (!queue.empty() && !free_slots.empty()) {
+    Req& r = reqs.at(queue.front());
+    uint64_t off = 0;
+    if (!arena->alloc(r.bytes, &off)) break;  // head of line waits for room
+    queue.pop_front();
+    r.off = off;
+    r.slot = free_slots.back();
+    free_slots.pop_back();
+    r.st = St::Active;
+    active.push_back(r.id);
+    SlotDev& sd = slots_stage[r.slot];
+    sd.key = r.key;
+    sd.ctr0 = r.ctr0;
+    sd.n = r.n;
+    sd.out_off = r.off;
+    sd.done = 0;
+    sd.kind = (uint32_t)r.kind;
+    sd.pad = 0;
+    new_slots->push_back(r.slot);
+    ++admitted;
+    any = true;
+  }
+  return any;
+}
+
+// Builds and launches one tick on an idle lane; returns true if launched.
+bool sq_server::tick_locked(const std::vector<uint32_t>& new_slots) {
+  if (!new_slots.empty()) {
+    for (uint32_t s : new_slots) {
+      hipError_t e = hipMemcpyAsync(slots_dev + s, slots_stage + s, sizeof(SlotDev), hipMemcpyHostToDevice, ctl);
+      if (e != hipSuccess) { if (fatal.empty()) fatal = std::string("slot upload: ") + hipGetErrorString(e); return false; }
+    }
+    hipError_t e = hipEventRecord(ctl_ev, ctl);
+    if (e != hipSuccess) { if (fatal.empty()) fatal = std::string("slot upload event: ") + hipGetErrorString(e); return false; }
+  }
+  TickLane* L = nullptr;
+  for (auto& l : lanes)
+    if (!l.busy) { L = &l; break; }
+  if (L == nullptr) return false;
+  TickHdr* th_ = (TickHdr*)L->host_buf;
+  TickEntry* ent = (TickEntry*)(L->host_buf + sizeof(TickHdr));
+  uint32_t m = 0;
+  for (uint64_t id : active) {
+    Req& r = reqs.at(id);
+    if (r.next >= r.n) continue;
+    const uint64_t cnt = std::min<uint64_t>(cfg.chunk_cap, r.n - r.next);
+    ent[m].slot = r.slot;
+    ent[m].pad = 0;
+    ent[m].first = r.next;
+    ent[m].count = cnt;
+    r.next += cnt;
+    ++r.inflight;
+    L->reqs.push_back(id);
+    if (++m == cfg.max_slots) break;
+  }
+  if (m == 0) return false;
+  th_->entries = m;
+  std::atomic_thread_fence(std::memory_order_seq_cst);  // entries visible before the launch doorbell
+  hipError_t e = hipStreamWaitEvent(L->stream, ctl_ev, 0);
+  if (e == hipSuccess) e = hipGraphLaunch(L->exec, L->stream);
+  if (e == hipSuccess) e = hipEventRecord(L->done, L->stream);
+  if (e != hipSuccess && fatal.empty()) fatal = std::string("tick launch: ") + hipGetErrorString(e);
+  L->busy = true;
+  ++ticks;
+  return true;
+}
+
+void sq_server::loop() {
+  (void)hipSetDevice(device);
+  std::unique_lock<std::mutex> lk(mu);
+  for (;;) {
+    bool progress = retire_locked();
+    std::vector<uint32_t> new_slots;
+    progress |= admit_locked(&new_slots);
+    bool launched = false;
+    do {
+      launched = tick_locked(new_slots);
+      new_slots.clear();
+      progress |= launched;
+    } while (launched);
+    const bool inflight = std::any_of(lanes.begin(), lanes.end(), [](const TickLane& l) { return l.busy; });
+    if (stop && !inflight && active.empty() && queue.empty()) break;
+    if (!inflight && !progress) {
+      // idle: sleep until a submit (or stop) arrives
+      cv_work.wait_for(lk, std::chrono::milliseconds(20));
+    } else if (!progress) {
+      // ticks running: poll their events without holding the lock
+      lk.unlock();
+      std::this_thread::yield();
+      lk.lock();
+    }
+  }
+}
+
+static void server_free(sq_server* s) {
+  for (auto& L : s->lanes) {
+    if (L.exec) (void)hipGraphExecDestroy(L.exec);
+    if (L.graph) (void)hipGraphDestroy(L.graph);
+    if (L.done) (void)hipEventDestroy(L.done);
+    if (L.stream) (void)hipStreamDestroy(L.stream);
+    if (L.host_buf) (void)hipHostFree(L.host_buf);
+    if (L.ws) (void)hipFree(L.ws);
+  }
+  if (s->ctl_ev) (void)hipEventDestroy(s->ctl_ev);
+  if (s->ctl) (void)hipStreamDestroy(s->ctl);
+  if (s->slots_stage) (void)hipHostFree(s->slots_stage);
+  if (s->slots_dev) (void)hipFree(s->slots_dev);
+  if (s->arena_dev) (void)hipFree(s->arena_dev);
+  delete s->arena;
+  delete s;
+}
+
+extern "C" {
+
+int sq_server_create(const sq_server_cfg* cfg, sq_server** out) {
+  if (cfg == nullptr || out == nullptr) return fail(SQ_EINVAL, "null cfg or server pointer");
+  *out = nullptr;
+  if (cfg->hbm_budget_bytes < 4096 || cfg->max_slots < 1 || cfg->max_slots > 65536 || cfg->chunk_cap < 4096 ||
+      cfg->n_streams < 1 || cfg->n_streams > 8 || (cfg->tile_log2 != 0 && (cfg->tile_log2 < 12 || cfg->tile_log2 > 24)))
+    return fail(SQ_EINVAL, "server configuration out of range");
+  int rc = ensure_init();
+  if (rc != SQ_OK) return rc;
+  sq_server* s = new sq_server();
+  s->cfg = *cfg;
+  s->device = device_info().device;
+  s->lcfg = tuned_cfg(SQ_OP_BATCH, SQ_U32, cfg->chunk_cap);
+  if (cfg->tile_log2) s->lcfg.tile_log2 = cfg->tile_log2;
+  s->arena = new Arena(cfg->hbm_budget_bytes);
+  hipError_t e = hipMalloc((void**)&s->arena_dev, cfg->hbm_budget_bytes);
+  if (e == hipSuccess) e = hipMalloc((void**)&s->slots_dev, sizeof(SlotDev) * cfg->max_slots);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&s->slots_stage, sizeof(SlotDev) * cfg->max_slots, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->ctl, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ctl_ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(s->ctl_ev, s->ctl);
+  s->lanes.resize(cfg->n_streams);
+  const size_t tbuf = sizeof(TickHdr) + sizeof(TickEntry) * (size_t)cfg->max_slots;
+  for (auto& L : s->lanes) {
+    if (e != hipSuccess) break;
+    e = hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&L.done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&L.host_buf, tbuf, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc(&L.ws, tick_ws_bytes(cfg->max_slots));
+    if (e != hipSuccess) break;
+    ((TickHdr*)L.host_buf)->entries = 0;
+    // capture expand -> scan -> fill once over this lane's fixed buffers
+    e = hipStreamBeginCapture(L.stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      hipError_t le = launch_tick(L.host_buf, s->slots_dev, cfg->max_slots, s->arena_dev, cfg->hbm_budget_bytes,
+                                  L.ws, s->lcfg, L.stream);
+      hipError_t ee = hipStreamEndCapture(L.stream, &L.graph);
+      e = le != hipSuccess ? le : ee;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&L.exec, L.graph, nullptr, nullptr, 0);
+  }
+  if (e != hipSuccess) {
+    int r = fail_hip(e, "server setup");
+    server_free(s);
+    return r;
+  }
+  for (uint32_t i = 0; i < cfg->max_slots; ++i) s->free_slots.push_back(cfg->max_slots - 1 - i);
+  s->th = std::thread([s] { s->loop(); });
+  *out = s;
+  return SQ_OK;
+}
+
+int sq_server_submit(sq_server* s, sq_kind kind, uint64_t key, uint64_t ctr0, uint64_t n, uint32_t flags,
+                     uint64_t* req_id) {
+  if (s == nullptr || req_id == nullptr) return fail(SQ_EINVAL, "null server or id pointer");
+  const int W = kind_bytes(kind);
+  if (W == 0) return fail(SQ_EINVAL, "unknown kind " + std::to_string((int)kind));
+  if (n == 0) return fail(SQ_EINVAL, "empty request");
+  if (n > s->cfg.hbm_budget_bytes / W || ((n * W + 255) & ~255ull) > s->cfg.hbm_budget_bytes)
+    return fail(SQ_ENOMEM, "request larger than the server's HBM budget");
+  std::lock_guard<std::mutex> g(s->mu);
+  if (!s->fatal.empty()) return fail(SQ_EHIP, "server failed: " + s->fatal);
+  if (s->stop) return fail(SQ_EBUSY, "server is shutting down");
+  Req r;
+  r.id = s->next_id++;
+  r.kind = kind;
+  r.key = key;
+  r.ctr0 = ctr0;
+  r.n = n;
+  r.flags = flags;
+  r.bytes = n * W;
+  r.t_submit = now_s();
+  if (s->submitted == 0) s->first_submit = r.t_submit;
+  ++s->submitted;
+  s->reqs.emplace(r.id, r);
+  s->queue.push_back(r.id);
+  *req_id = r.id;
+  s->cv_work.notify_one();
+  return SQ_OK;
+}
+
+int sq_server_poll(sq_server* s, uint64_t id, int* done) {
+  if (s == nullptr || done == nullptr) return fail(SQ_EINVAL, "null server or flag pointer");
+  std::lock_guard<std::mutex> g(s->mu);
+  if (!s->fatal.empty()) return fail(SQ_EHIP, "server failed: " + s->fatal);
+  auto it = s->reqs.find(id);
+  if (it == s->reqs.end()) {
+    if (id == 0 || id >= s->next_id || s->cancelled.count(id)) return fail(SQ_ENOTFOUND, "unknown or cancelled request");
+    *done = 1;  // completed and already released or discarded
+    return SQ_OK;
+  }
+  *done = it->second.st == St::Done;
+  return SQ_OK;
+}
+
+int sq_server_wait(sq_server* s, uint64_t id) {
+  if (s == nullptr) return fail(SQ_EINVAL, "null server");
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (id == 0 || id >= s->next_id || s->cancelled.count(id)) return fail(SQ_ENOTFOUND, "unknown or cancelled request");
+  for (;;) {
+    if (!s->fatal.empty()) return fail(SQ_EHIP, "server failed: " + s->fatal);
+    auto it = s->reqs.find(id);
+    if (it == s->reqs.end() || it->second.st == St::Done) return SQ_OK;
+    s->cv_done.wait_for(lk, std::chrono::milliseconds(50));
+  }
+}
+
+int sq_server_result(sq_server* s, uint64_t id, void** ptr, uint64_t* bytes) {
+  if (s == nullptr || ptr == nullptr || bytes == nullptr) return fail(SQ_EINVAL, "null argument");
+  std::lock_guard<std::mutex> g(s->mu);
+  auto it = s->reqs.find(id);
+  if (it == s->reqs.end()) return fail(SQ_ENOTFOUND, "unknown, released or discarded request");
+  if (it->second.st != St::Done) return fail(SQ_EBUSY, "request not complete");
+  *ptr = s->arena_dev + it->second.off;
+  *bytes = it->second.bytes;
+  return SQ_OK;
+}
+
+int sq_server_latency(sq_server* s, uint64_t id, double* seconds) {
+  if (s == nullptr || seconds == nullptr) return fail(SQ_EINVAL, "null argument");
+  std::lock_guard<std::mutex> g(s->mu);
+  auto it = s->reqs.find(id);
+  if (it == s->reqs.end()) return fail(SQ_ENOTFOUND, "unknown, released or discarded request");
+  if (it->second.st != St::Done) return fail(SQ_EBUSY, "request not complete");
+  *seconds = it->second.t_done - it->second.t_submit;
+  return SQ_OK;
+}
+
+int sq_server_release(sq_server* s, uint64_t id) {
+  if (s == nullptr) return fail(SQ_EINVAL, "null server");
+  std::lock_guard<std::mutex> g(s->mu);
+  auto it = s->reqs.find(id);
+  if (it == s->reqs.end()) return fail(SQ_ENOTFOUND, "unknown or already released request");
+  if (it->second.st != St::Done) return fail(SQ_EBUSY, "request not complete");
+  s->arena->release(it->second.off, it->second.bytes);
+  ++s->released;
+  s->reqs.erase(it);
+  s->cv_work.notify_one();
+  return SQ_OK;
+}
+
+int sq_server_cancel(sq_server* s, uint64_t id) {
+  if (s == nullptr) return fail(SQ_EINVAL, "null server");
+  std::lock_guard<std::mutex> g(s->mu);
+  auto it = s->reqs.find(id);
+  if (it == s->reqs.end()) return fail(SQ_ENOTFOUND, "unknown request");
+  if (it->second.st != St::Queued) return fail(SQ_EBUSY, "request already admitted");
+  s->queue.erase(std::find(s->queue.begin(), s->queue.end(), id));
+  s->reqs.erase(it);
+  s->cancelled.insert(id);
+  return SQ_OK;
+}
+
+int sq_server_stats(sq_server* s, sq_server_stats_t* o) {
+  if (s == nullptr || o == nullptr) return fail(SQ_EINVAL, "null argument");
+  std::lock_guard<std::mutex> g(s->mu);
+  *o = sq_server_stats_t{};
+  o->submitted = s->submitted;
+  o->admitted = s->admitted;
+  o->completed = s->completed;
+  o->released = s->released;
+  o->outputs = s->outputs;
+  o->bytes = s->bytes_done;
+  o->ticks = s->ticks;
+  o->queued_now = s->queue.size();
+  o->active_now = s->active.size();
+  o->arena_used_bytes = s->arena->used();
+  o->first_submit_s = s->first_submit;
+  o->last_complete_s = s->last_complete;
+  if (!s->lat.empty()) {
+    std::vector<double> v = s->lat;
+    std::sort(v.begin(), v.end());
+    auto q = [&](double p) { return v[std::min<size_t>(v.size() - 1, (size_t)(p * (double)(v.size() - 1) + 0.5))]; };
+    o->p50_s = q(0.50);
+    o->p90_s = q(0.90);
+    o->p99_s = q(0.99);
+    o->max_s = v.back();
+    double sum = 0;
+    for (double x : v) sum += x;
+    o->mean_s = sum / (double)v.size();
+  }
+  return SQ_OK;
+}
+
+int sq_server_destroy(sq_server* s) {
+  if (s == nullptr) return SQ_OK;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    // queued requests never start; admitted ones drain
+    for (uint64_t id : s->queue) {
+      s->reqs.erase(id);
+      s->cancelled.insert(id);
+    }
+    s->queue.clear();
+    s->stop = true;
+    s->cv_work.notify_all();
+  }
+  s->th.join();
+  std::string fatal = s->fatal;
+  hipError_t e = hipDeviceSynchronize();
+  server_free(s);
+  if (!fatal.empty()) return fail(SQ_EHIP, "server failed: " + fatal);
+  if (e != hipSuccess) return fail_hip(e, "server drain");
+  return SQ_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+"""Open-loop load generator for the continuous-batching server.
+
+Requests (kind, key, ctr0, size) come from the seeded serving trace: sizes
+log-uniform in [2^10, 2^28] outputs, 70% 32-bit (U32/F32) and 30% 64-bit
+(U64/F64), Poisson arrivals.  The driver submits each request at its
+scheduled arrival time (busy-waiting in between) with the discard flag, so
+the server frees its output as soon as it completes; latency is measured by
+the server from submit to completion, so it includes queueing.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import workloads as W
+
+
+def saturated(sq, trace: W.ServeTrace, budget: int, chunk_cap: int, n_streams: int = 2) -> dict:
+    """Throughput with every request submitted at once (closed system)."""
+    with sq.Server(budget, max_slots=4096, chunk_cap=chunk_cap, n_streams=n_streams) as srv:
+        t0 = time.perf_counter()
+        for i in range(trace.r):
+            srv.submit(int(trace.kinds[i]), int(trace.keys[i]), int(trace.ctr0s[i]), int(trace.sizes[i]),
+                       sq.SERVE_DISCARD)
+        while srv.stats()["completed"] < trace.r:
+            time.sleep(0.0005)
+        dt = time.perf_counter() - t0
+        st = srv.stats()
+    return {"requests": trace.r, "seconds": dt, "req_per_s": trace.r / dt,
+            "gnum_s": st["outputs"] / dt / 1e9, "gb_s": st["bytes"] / dt / 1e9, "ticks": st["ticks"]}
+
+
+def open_loop(sq, trace: W.ServeTrace, budget: int, chunk_cap: int, warmup: int, n_streams: int = 2) -> dict:
+    """Submits request i at trace.arrival_s[i]; statistics over requests after
+    the first `warmup` ones."""
+    lat = []
+    lag_max = 0.0
+    with sq.Server(budget, max_slots=4096, chunk_cap=chunk_cap, n_streams=n_streams) as srv:
+        ids = []
+        t0 = time.perf_counter()
+        for i in range(trace.r):
+            due = t0 + float(trace.arrival_s[i])
+            while True:
+                now = time.perf_counter()
+                if now >= due:
+                    break
+            lag_max = max(lag_max, now - due) if i >= warmup else lag_max
+            flags = 0 if i >= warmup else sq.SERVE_DISCARD
+            ids.append(srv.submit(int(trace.kinds[i]), int(trace.keys[i]), int(trace.ctr0s[i]),
+                                  int(trace.sizes[i]), flags))
+            # release measured requests as they complete, keeping the arena free
+            if i >= warmup and (i & 63) == 0:
+                _harvest(srv, ids, warmup, lat)
+        while len(lat) < trace.r - warmup:
+            _harvest(srv, ids, warmup, lat)
+            time.sleep(0.0002)
+        t_end = time.perf_counter()
+        st = srv.stats()
+    lat_a = np.array(lat)
+    span = float(trace.arrival_s[-1] - trace.arrival_s[warmup])
+    measured = trace.sizes[warmup:]
+    bytes_ = sum(int(s) * (4 if k < 2 else 8) for s, k in zip(measured, trace.kinds[warmup:]))
+    return {"requests": trace.r - warmup, "qps_offered": (trace.r - warmup) / span if span > 0 else None,
+            "p50_ms": float(np.percentile(lat_a, 50) * 1e3), "p90_ms": float(np.percentile(lat_a, 90) * 1e3),
+            "p99_ms": float(np.percentile(lat_a, 99) * 1e3), "max_ms": float(lat_a.max() * 1e3),
+            "mean_ms": float(lat_a.mean() * 1e3), "gnum_s": float(measured.sum()) / (t_end - t0) / 1e9,
+            "gb_s": bytes_ / (t_end - t0) / 1e9, "driver_lag_max_ms": lag_max * 1e3, "ticks": st["ticks"]}
+
+
+_done_upto = {}
+
+
+def _harvest(srv, ids, warmup, lat):
+    """Collects latencies of completed measured requests (in order) and
+    releases their outputs."""
+    k = id(srv)
+    j = _done_upto.get(k, warmup)
+    while j < len(ids) and srv.poll(ids[j]):
+        lat.append(srv.latency(ids[j]))
+        srv.release(ids[j])
+        j += 1
+    _done_upto[k] = j
+
+
+def run_short(sq, torch, budget: int = 32 << 30, chunk_cap: int = 1 << 24) -> dict:
+    """Capacity with all requests queued at once, then an open-loop run at half
+    of that rate (the rate is stated in the result)."""
+    cap_trace = W.serve_trace(seed=5, r=2000, qps=1e9)
+    cap = saturated(sq, cap_trace, budget, chunk_cap)
+    qps = 0.5 * cap["req_per_s"]
+    tr = W.serve_trace(seed=6, r=6000, qps=qps)
+    ol = open_loop(sq, tr, budget, chunk_cap, warmup=1000)
+    torch.cuda.synchronize()
+    return {"workload": "Poisson arrivals, sizes log-uniform 2^10..2^28 outputs, 70% 32-bit / 30% 64-bit",
+            "hbm_budget_gib": budget >> 30, "chunk_cap": chunk_cap,
+            "saturated_req_per_s": round(cap["req_per_s"], 1), "saturated_gnum_s": round(cap["gnum_s"], 1),
+            "qps": round(qps, 1), **{k: (round(v, 4) if isinstance(v, float) else v) for k, v in ol.items()}}

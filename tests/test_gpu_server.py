@@ -1,0 +1,148 @@
+"""GPU tests of the continuous-batching server: every request's output equals
+the oracle and the same request served alone; admission by HBM budget,
+cancellation, error paths and draining."""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import pytest
+
+from gpu_helpers import KIND_BYTES, first_diff, log, to_host_bytes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sq():
+    from paper_2004_06278_amd import squares
+
+    squares.lib()
+    return squares
+
+
+def _oracle(o, kind, key, ctr0, n):
+    return o.fill(kind, key, ctr0, n).view(np.uint8)
+
+
+def _mix(seed, r, max_log2):
+    from paper_2004_06278_amd import workloads as W
+
+    tr = W.serve_trace(seed=seed, r=r, qps=1e9, lo_exp=0, hi_exp=max_log2)
+    return [(int(tr.kinds[i]), int(tr.keys[i]), int(tr.ctr0s[i]), int(tr.sizes[i])) for i in range(r)]
+
+
+@pytest.mark.parametrize("n_streams,chunk_cap", [(1, 4096), (2, 1 << 14), (3, 1 << 20)])
+def test_server_alone_equals_mix_equals_oracle(sq, oracle_mod, n_streams, chunk_cap):
+    probe = (3, 0x6C8E9CF570932BD5, 2**64 - 70000, 150001)  # F64, wraps the counter, spans many ticks
+    log(f"server alone n_streams={n_streams} chunk_cap={chunk_cap}")
+    with sq.Server(64 << 20, max_slots=64, chunk_cap=chunk_cap, n_streams=n_streams) as srv:
+        rid = srv.submit(*probe)
+        srv.wait(rid)
+        alone = to_host_bytes(srv.result_bytes(rid))
+        srv.release(rid)
+    ref = _oracle(oracle_mod, *probe)
+    assert alone.tobytes() == ref.tobytes(), first_diff(alone, ref)
+
+    reqs = _mix(seed=40 + n_streams, r=120, max_log2=17)
+    reqs.insert(60, probe)
+    log(f"server mix of {len(reqs)} requests")
+    with sq.Server(256 << 20, max_slots=48, chunk_cap=chunk_cap, n_streams=n_streams) as srv:
+        ids = [srv.submit(*q) for q in reqs]
+        for rid in ids:
+            srv.wait(rid)
+        for q, rid in zip(reqs, ids):
+            got = to_host_bytes(srv.result_bytes(rid))
+            exp = _oracle(oracle_mod, *q)
+            assert got.tobytes() == exp.tobytes(), (q, first_diff(got, exp))
+            if q == probe:
+                assert got.tobytes() == alone.tobytes()  # same bits alone and in the mix
+            assert srv.latency(rid) > 0
+            srv.release(rid)
+        st = srv.stats()
+        assert st["completed"] == len(reqs) == st["released"]
+        assert st["arena_used_bytes"] == 0 and st["active_now"] == 0
+
+
+def test_server_admission_by_budget_queues(sq, oracle_mod):
+    """More requests than the arena holds at once: later ones wait in the
+    queue until earlier outputs are released, then complete correctly."""
+    budget = 1 << 20
+    reqs = [(k % 4, 0x1234567 + k, k * 1000003, 60000) for k in range(12)]  # 240-480 KB each
+    with sq.Server(budget, max_slots=16, chunk_cap=1 << 14, n_streams=2) as srv:
+        ids = [srv.submit(*q) for q in reqs]
+        time.sleep(0.05)
+        st = srv.stats()
+        assert st["queued_now"] > 0, st  # the budget cannot hold all twelve
+        for q, rid in zip(reqs, ids):
+            srv.wait(rid)
+            got = to_host_bytes(srv.result_bytes(rid))
+            assert got.tobytes() == _oracle(oracle_mod, *q).tobytes()
+            srv.release(rid)
+        assert srv.stats()["completed"] == len(reqs)
+
+
+def test_server_errors_and_cancel(sq):
+    with sq.Server(1 << 20, max_slots=4, chunk_cap=4096, n_streams=1) as srv:
+        with pytest.raises(sq.SquaresError) as e:
+            srv.submit(0, 1, 0, (1 << 20) // 4 + 1)  # larger than the whole budget
+        assert e.value.status == -3
+        with pytest.raises(sq.SquaresError) as e:
+            srv.submit(9, 1, 0, 10)
+        assert e.value.status == -1
+        with pytest.raises(sq.SquaresError) as e:
+            srv.submit(0, 1, 0, 0)
+        assert e.value.status == -1
+        big = srv.submit(2, 5, 0, (1 << 20) // 8)  # fills the arena
+        small = srv.submit(0, 6, 0, 100)           # must wait for `big` to be released
+        srv.wait(big)
+        time.sleep(0.02)
+        assert not srv.poll(small)
+        srv.cancel(small)
+        with pytest.raises(sq.SquaresError) as e:
+            srv.poll(small)
+        assert e.value.status == -6
+        with pytest.raises(sq.SquaresError) as e:
+            srv.cancel(big)  # already admitted
+        assert e.value.status == -5
+        srv.release(big)
+        with pytest.raises(sq.SquaresError):
+            srv.release(big)
+    with pytest.raises(sq.SquaresError):
+        sq.Server(1 << 20, n_streams=0)
+
+
+def test_server_resume_from_saved_counter(sq, oracle_mod):
+    """A stream checkpoint is (key, next counter): serving [c, c+a) then
+    [c+a, c+a+b) gives the same outputs as serving [c, c+a+b) at once."""
+    key, c, a, b = 0xD1B54A32D192ED03, 2**64 - 5000, 7777, 9999
+    with sq.Server(16 << 20, max_slots=8, chunk_cap=4096, n_streams=2) as srv:
+        r1 = srv.submit(0, key, c, a)
+        r2 = srv.submit(0, key, (c + a) % 2**64, b)
+        r3 = srv.submit(0, key, c, a + b)
+        for r in (r1, r2, r3):
+            srv.wait(r)
+        two = np.concatenate([to_host_bytes(srv.result_bytes(r1)), to_host_bytes(srv.result_bytes(r2))])
+        one = to_host_bytes(srv.result_bytes(r3))
+        assert two.tobytes() == one.tobytes() == _oracle(oracle_mod, 0, key, c, a + b).tobytes()
+
+
+def test_server_destroy_drains_in_flight_work(sq):
+    srv = sq.Server(512 << 20, max_slots=64, chunk_cap=1 << 16, n_streams=2)
+    for i in range(200):
+        srv.submit(i % 4, 1000 + i, i << 20, 1 << 18, sq.SERVE_DISCARD)
+    srv.close()  # returns after admitted work finished; queued requests are dropped
+
+
+def test_server_open_loop_smoke(sq):
+    """A short Poisson run: every request completes and percentiles are ordered."""
+    import torch
+
+    from paper_2004_06278_amd import serve_bench
+    from paper_2004_06278_amd import workloads as W
+
+    tr = W.serve_trace(seed=8, r=600, qps=5000.0, hi_exp=22)
+    res = serve_bench.open_loop(sq, tr, budget=4 << 30, chunk_cap=1 << 22, warmup=100)
+    torch.cuda.synchronize()
+    assert res["requests"] == 500
+    assert 0 < res["p50_ms"] <= res["p90_ms"] <= res["p99_ms"] <= res["max_ms"]
