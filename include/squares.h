@@ -156,11 +156,12 @@ int sq_reduce_cfg(sq_kind kind, uint64_t key, uint64_t ctr0, uint64_t n, sq_sum_
  * overlap.  The kernels check every descriptor on the device: a stream with
  * an unknown kind, a misaligned offset or a range past out_bytes is skipped
  * (nothing written) and counted; sq_batch_errors() reads that count.
- * `ws` needs sq_batch_workspace_bytes(m) bytes (16-byte aligned).
+ * `ws` needs sq_batch_workspace_bytes(m, out_bytes) bytes (16-byte aligned):
+ * a header, the tile scan and a tile-to-stream map sized for the arena.
  * The work is split into tiles of 2^tile_log2 outputs; a tile scan and one
  * persistent kernel run on `stream`.
  * ------------------------------------------------------------------------ */
-size_t sq_batch_workspace_bytes(uint32_t m);
+size_t sq_batch_workspace_bytes(uint32_t m, uint64_t out_bytes);
 int sq_fill_batch(const uint64_t *keys, const uint64_t *ctr0s, const uint64_t *lens,
                   const uint64_t *offs, const uint8_t *kinds, uint32_t m, void *out,
                   uint64_t out_bytes, void *ws, size_t ws_bytes, void *stream);

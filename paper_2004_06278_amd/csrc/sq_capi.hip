@@ -148,10 +148,10 @@ int sq_reduce(sq_kind kind, uint64_t key, uint64_t ctr0, uint64_t n, sq_sum_resu
 }
 
 // ---------------------------------------------------------------- batch
-size_t sq_batch_workspace_bytes(uint32_t m) { return batch_ws_bytes(m); }
+size_t sq_batch_workspace_bytes(uint32_t m, uint64_t out_bytes) { return batch_ws_bytes(m, out_bytes); }
 
 static int check_batch(const uint64_t* keys, const uint64_t* ctr0s, const uint64_t* lens, const uint64_t* offs,
-                       const uint8_t* kinds, uint32_t m, void* out, void* ws, size_t ws_bytes) {
+                       const uint8_t* kinds, uint32_t m, void* out, uint64_t out_bytes, void* ws, size_t ws_bytes) {
   if (m == 0) return SQ_OK;
   if (!keys || !ctr0s || !lens || !offs || !kinds || !out || !ws)
     return fail(SQ_EINVAL, "null descriptor, output or workspace pointer");
@@ -159,7 +159,8 @@ static int check_batch(const uint64_t* keys, const uint64_t* ctr0s, const uint64
     return fail(SQ_EALIGN, "descriptor arrays must be 8-byte aligned");
   if (((uintptr_t)out & 7) != 0 || ((uintptr_t)ws & 15) != 0)
     return fail(SQ_EALIGN, "arena must be 8-byte and workspace 16-byte aligned");
-  if (ws_bytes < batch_ws_bytes(m)) return fail(SQ_ENOMEM, "batch workspace smaller than sq_batch_workspace_bytes()");
+  if (ws_bytes < batch_ws_bytes(m, out_bytes))
+    return fail(SQ_ENOMEM, "batch workspace smaller than sq_batch_workspace_bytes()");
   return SQ_OK;
 }
 
@@ -171,7 +172,7 @@ static uint64_t mean_bucket_len(uint32_t m) {
 int sq_fill_batch_cfg(const uint64_t* keys, const uint64_t* ctr0s, const uint64_t* lens, const uint64_t* offs,
                       const uint8_t* kinds, uint32_t m, void* out, uint64_t out_bytes, void* ws, size_t ws_bytes,
                       const sq_launch_cfg* cfg, void* stream) {
-  int rc = check_batch(keys, ctr0s, lens, offs, kinds, m, out, ws, ws_bytes);
+  int rc = check_batch(keys, ctr0s, lens, offs, kinds, m, out, out_bytes, ws, ws_bytes);
   if (rc != SQ_OK || m == 0) return rc;
   if (cfg == nullptr || !cfg_valid(SQ_OP_BATCH, *cfg)) return fail(SQ_EINVAL, "invalid batch launch configuration");
   SQ_INIT_OR_RETURN();
@@ -235,7 +236,7 @@ int sq_batch_plan_create(const uint64_t* keys, const uint64_t* ctr0s, const uint
   if (plan == nullptr) return fail(SQ_EINVAL, "null plan pointer");
   *plan = nullptr;
   if (m == 0) return fail(SQ_EINVAL, "a plan needs m > 0");
-  int rc = check_batch(keys, ctr0s, lens, offs, kinds, m, out, ws, ws_bytes);
+  int rc = check_batch(keys, ctr0s, lens, offs, kinds, m, out, out_bytes, ws, ws_bytes);
   if (rc != SQ_OK) return rc;
   SQ_INIT_OR_RETURN();
   const sq_launch_cfg c = cfg ? *cfg : tuned_cfg(SQ_OP_BATCH, SQ_U32, mean_bucket_len(m));

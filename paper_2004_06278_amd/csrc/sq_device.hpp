@@ -25,19 +25,31 @@ namespace sqd {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-// Returns v unchanged, but opaque to the optimizer.  y advances by key per
-// counter, so without this LLVM treats round 1's y*y + y as a polynomial in
-// the loop counter and strength-reduces it into extra multiply-adds.  The
-// empty asm emits no instruction.
+// Returns v unchanged, but opaque to the optimizer; the empty asm emits no
+// instruction.  Used on per-chunk base values so that loop-strength
+// reduction does not turn each unrolled vector's Weyl term and address into
+// an induction variable of its own.
 __device__ __forceinline__ uint64_t opaque(uint64_t v) {
   asm volatile("" : "+v"(v));
   return v;
 }
 
+// xl*xl + a as exactly one v_mad_u64_u32 (its carry-out goes to vcc, which
+// nothing reads).  Written as a non-volatile asm statement so LLVM can still
+// schedule it, but can neither duplicate it nor, since y advances by key per
+// counter, strength-reduce round 1's y*y + y into a polynomial in the loop
+// counter (both happen with plain C).  The destination is early-clobber: it
+// must not overlap the sources.
+__device__ __forceinline__ uint64_t sq_lo_plus(uint32_t xl, uint64_t a) {
+  uint64_t m;
+  asm("v_mad_u64_u32 %0, vcc, %1, %1, %2" : "=&v"(m) : "v"(xl), "v"(a) : "vcc");
+  return m;
+}
+
 // rot32(x*x + a)
 __device__ __forceinline__ uint64_t round_rot(uint64_t x, uint64_t a) {
   const uint32_t xl = (uint32_t)x, xh = (uint32_t)(x >> 32);
-  const uint64_t m = (uint64_t)xl * xl + a;                       // v_mad_u64_u32
+  const uint64_t m = sq_lo_plus(xl, a);                           // v_mad_u64_u32
   const uint32_t hi = (uint32_t)(m >> 32) + ((xl * xh) << 1);     // v_mul_lo_u32, v_lshl_add_u32
   return ((uint64_t)(uint32_t)m << 32) | hi;                      // halves swapped
 }
@@ -45,7 +57,7 @@ __device__ __forceinline__ uint64_t round_rot(uint64_t x, uint64_t a) {
 // x*x + a without the rotation, as (lo, hi) words
 __device__ __forceinline__ void round_norot(uint64_t x, uint64_t a, uint32_t& lo, uint32_t& hi) {
   const uint32_t xl = (uint32_t)x, xh = (uint32_t)(x >> 32);
-  const uint64_t m = (uint64_t)xl * xl + a;
+  const uint64_t m = sq_lo_plus(xl, a);
   lo = (uint32_t)m;
   hi = (uint32_t)(m >> 32) + ((xl * xh) << 1);
 }
@@ -53,13 +65,13 @@ __device__ __forceinline__ void round_norot(uint64_t x, uint64_t a, uint32_t& lo
 // Upper 32 bits of x*x + a
 __device__ __forceinline__ uint32_t round_hi(uint64_t x, uint64_t a) {
   const uint32_t xl = (uint32_t)x, xh = (uint32_t)(x >> 32);
-  const uint64_t m = (uint64_t)xl * xl + a;
+  const uint64_t m = sq_lo_plus(xl, a);
   return (uint32_t)(m >> 32) + ((xl * xh) << 1);
 }
 
 // squares32 from its Weyl terms y = ctr*key, z = (ctr+1)*key.
 __device__ __forceinline__ uint32_t sq32(uint64_t y, uint64_t z) {
-  uint64_t x = round_rot(opaque(y), y);  // round 1 (x starts as y)
+  uint64_t x = round_rot(y, y);  // round 1 (x starts as y)
   x = round_rot(x, z);           // round 2
   x = round_rot(x, y);           // round 3
   return round_hi(x, z);         // round 4: upper half of x*x + z
@@ -68,7 +80,7 @@ __device__ __forceinline__ uint32_t sq32(uint64_t y, uint64_t z) {
 // squares64: round 4 keeps t = x*x + z whole; round 5 squares rot32(t), adds
 // y and its upper 32 bits are XORed into the low word of t.
 __device__ __forceinline__ uint64_t sq64(uint64_t y, uint64_t z) {
-  uint64_t x = round_rot(opaque(y), y);
+  uint64_t x = round_rot(y, y);
   x = round_rot(x, z);
   x = round_rot(x, y);
   uint32_t tl, th;

@@ -49,7 +49,8 @@ struct BatchDesc {
   uint64_t out_bytes;
 };
 
-// Workspace header written by the tile scan; followed by tile_start[m+1].
+// Workspace header written by the tile scan; followed by tile_start[m+1]
+// and the tile -> stream map.
 struct BatchHdr {
   uint64_t total_tiles;
   uint32_t errors;
@@ -57,7 +58,8 @@ struct BatchHdr {
   uint64_t pad[6];
 };
 static_assert(sizeof(BatchHdr) == 64, "header is 64 bytes");
-size_t batch_ws_bytes(uint32_t m);
+uint64_t batch_max_tiles(uint32_t m, uint64_t out_bytes);
+size_t batch_ws_bytes(uint32_t m, uint64_t out_bytes);
 hipError_t launch_batch(const BatchDesc& d, void* ws, const sq_launch_cfg& cfg, hipStream_t s);
 
 // Serving tick: entries (slot, first output, count) over a device slot table.
@@ -86,7 +88,7 @@ struct TickHdr {
 static_assert(sizeof(TickHdr) == 64, "tick header is 64 bytes");
 // tick buffer = TickHdr + max_entries TickEntry (device); tick ws holds the
 // expanded batch descriptors and tile scan for up to max_entries streams.
-size_t tick_ws_bytes(uint32_t max_entries);
+size_t tick_ws_bytes(uint32_t max_entries, uint64_t arena_bytes);
 hipError_t launch_tick(const void* tick_buf, SlotDev* slots, uint32_t max_entries, unsigned char* arena,
                        uint64_t arena_bytes, void* tick_ws, const sq_launch_cfg& cfg, hipStream_t s);
 

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <map>
 #include <mutex>
+#include <type_traits>
 
 #include "sq_device.hpp"
 #include "sq_internal.hpp"
@@ -30,19 +31,22 @@ struct FillArgs {
   uint64_t nchunks;     // ceil(nvec / (block * U))
   uint64_t y_body;      // (ctr0 + head) * key: first Weyl term of the body
   uint64_t ekey;        // E * key: Weyl step from one vector to the next
-  uint32_t head;        // elements before the 16-byte aligned body (0..3)
+  uint32_t head;        // elements before the 1 KiB aligned body (< 1024 / W)
   uint32_t tail;        // elements after the last full vector (0..3)
   uint32_t xcd_map;     // chunk order, see sq_launch_cfg
   uint32_t pad;
 };
 
+// Elements before the body (up to the first 1 KiB boundary) and after its
+// last full vector, one element store each, by workgroup 0.
 template <int K>
 __device__ __forceinline__ void fill_edges(const FillArgs& a) {
   constexpr int W = Kind<K>::W, E = 16 / W;
-  const uint32_t t = threadIdx.x;
-  if (blockIdx.x != 0 || t >= a.head + a.tail) return;
-  const uint64_t i = t < a.head ? (uint64_t)t : a.head + a.nvec * E + (t - a.head);
-  store_one<K>(a.out + i * W, (a.ctr0 + i) * a.key, a.key);
+  if (blockIdx.x != 0) return;
+  for (uint32_t t = threadIdx.x; t < a.head + a.tail; t += blockDim.x) {
+    const uint64_t i = t < a.head ? (uint64_t)t : a.head + a.nvec * E + (t - a.head);
+    store_one<K>(a.out + i * W, (a.ctr0 + i) * a.key, a.key);
+  }
 }
 
 // Chunk c covers vectors [c*B*U, (c+1)*B*U) of the body; lane tid writes
@@ -54,9 +58,11 @@ __device__ __forceinline__ void fill_chunk(const FillArgs& a, uint64_t c) {
   const uint32_t B = blockDim.x, tid = threadIdx.x;
   unsigned char* body = a.out + (uint64_t)a.head * W;
   const uint64_t v0 = c * B * U + tid;
-  uint64_t y = a.y_body + v0 * a.ekey;
+  // opaque: otherwise loop-strength reduction keeps a separate induction
+  // variable (two VGPRs each) for every unrolled vector's y and address
+  uint64_t y = opaque(a.y_body + v0 * a.ekey);
   const uint64_t step = (uint64_t)B * a.ekey;
-  u32x4* p = (u32x4*)(body + v0 * 16);
+  u32x4* p = (u32x4*)opaque((uint64_t)(body + v0 * 16));
   if ((c + 1) * B * U <= a.nvec) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -168,26 +174,30 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a) {
       y = z;
     }
   } else {
-    // terms < 2^53 (F64), < 2^32 (U32), < 2^24 (F32)
-    constexpr uint64_t FLUSH = K == 3 ? 1024 : (1u << 20);
+    // Terms < 2^53 (F64) and < 2^32 (U32) go into a 64-bit partial that is
+    // flushed before it could overflow.  F32 terms are < 2^24, so 256 of them
+    // fit a 32-bit partial: one 32-bit add per output instead of a 64-bit one.
+    typedef typename std::conditional<K == 1, uint32_t, uint64_t>::type Part;
+    constexpr uint64_t FLUSH = K == 3 ? 1024 : (K == 1 ? 256 : (1u << 20));
     uint64_t i = 0;
     while (i < cnt) {
       const uint64_t len = cnt - i < FLUSH ? cnt - i : FLUSH;
-      uint64_t s = 0, j = 0;
+      Part s = 0;
+      uint64_t j = 0;
       for (; j + U <= len; j += U) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const uint64_t z = y + key;
-          s += sum_term<K>(y, z);
+          s += (Part)sum_term<K>(y, z);
           y = z;
         }
       }
       for (; j < len; ++j) {
         const uint64_t z = y + key;
-        s += sum_term<K>(y, z);
+        s += (Part)sum_term<K>(y, z);
         y = z;
       }
-      add128(lo, hi, s, 0);
+      add128(lo, hi, (uint64_t)s, 0);
       i += len;
     }
   }
@@ -253,9 +263,12 @@ __device__ __forceinline__ uint64_t stream_tiles(const sqi::BatchDesc& d, uint32
 }
 
 // One workgroup: exclusive scan of per-stream tile counts into ts[0..m],
-// plus the total and the count of skipped streams in the header.
+// plus the total and the count of skipped streams in the header.  If the
+// tiles would exceed the map's capacity (only possible when streams overlap,
+// which the interface forbids) nothing is scheduled and every stream counts
+// as skipped.
 __global__ __launch_bounds__(1024) void k_batch_scan(sqi::BatchDesc d, const uint32_t* m_dev, uint32_t lg,
-                                                     sqi::BatchHdr* hdr, uint64_t* ts) {
+                                                     uint64_t max_tiles, sqi::BatchHdr* hdr, uint64_t* ts) {
   __shared__ uint64_t part[1024];
   __shared__ uint32_t errs;
   const uint32_t m = m_dev ? *m_dev : d.m;
@@ -284,58 +297,85 @@ __global__ __launch_bounds__(1024) void k_batch_scan(sqi::BatchDesc d, const uin
     run += stream_tiles(d, s, lg, &dummy);
   }
   if (tid == B - 1) {
+    const bool fits = part[B - 1] <= max_tiles;
     ts[m] = part[B - 1];
-    hdr->total_tiles = part[B - 1];
+    hdr->total_tiles = fits ? part[B - 1] : 0;
     hdr->m = m;
-    hdr->errors = errs;
+    hdr->errors = fits ? errs : m;
   }
 }
 
-// The workgroup fills `cnt` outputs of kind K from counter ctr at p
-// (element-aligned): a head up to the next 16-byte boundary, full vectors,
-// and a tail, element stores at both ends.
-template <int K>
-__device__ __forceinline__ void fill_range(uint64_t key, uint64_t ctr, uint64_t cnt, unsigned char* p) {
-  constexpr int W = Kind<K>::W, E = 16 / W;
-  const uint32_t tid = threadIdx.x, B = blockDim.x;
-  const uint32_t mis = (uint32_t)((uintptr_t)p & 15u);
-  uint64_t head = mis ? (16u - mis) / W : 0;
-  if (head > cnt) head = cnt;
-  const uint64_t nvec = (cnt - head) / E;
-  const uint64_t tail = cnt - head - nvec * E;
-  if (tid < head) store_one<K>(p + (uint64_t)tid * W, (ctr + tid) * key, key);
-  if (tid < tail) {
-    const uint64_t i = head + nvec * E + tid;
-    store_one<K>(p + i * W, (ctr + i) * key, key);
-  }
-  unsigned char* body = p + head * W;
-  const uint64_t ekey = (uint64_t)E * key;
-  uint64_t y = (ctr + head + (uint64_t)tid * E) * key;
-  const uint64_t step = (uint64_t)B * ekey;
-#pragma unroll 1
-  for (uint64_t v = tid; v < nvec; v += B) {
-    *(u32x4*)(body + v * 16) = gen_vec<K>(y, key);
-    y += step;
-    __builtin_amdgcn_sched_barrier(0);
-  }
-}
-
-// Persistent: workgroup g takes tiles g, g + grid, ...; each tile is mapped
-// to its stream by binary search over the tile scan (wave-uniform, so the
-// loads go through the scalar cache).
-__global__ __launch_bounds__(1024) void k_batch_fill(sqi::BatchDesc d, uint32_t lg, const sqi::BatchHdr* hdr,
-                                                     const uint64_t* ts) {
+// tile -> stream map: map[t] = the stream whose tiles include t (largest s
+// with ts[s] <= t), one binary search per tile, all tiles in parallel.
+__global__ __launch_bounds__(256) void k_batch_map(const sqi::BatchHdr* hdr, const uint64_t* ts, uint32_t* map) {
   const uint64_t total = hdr->total_tiles;
   const uint32_t m = hdr->m;
-  const uint64_t T = 1ull << lg;
-#pragma unroll 1
-  for (uint64_t t = blockIdx.x; t < total; t += gridDim.x) {
+  for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < total;
+       t += (uint64_t)gridDim.x * blockDim.x) {
     uint32_t lo = 0, hi = m - 1;
     while (lo < hi) {
       const uint32_t mid = (lo + hi + 1) >> 1;
       if (ts[mid] <= t) lo = mid; else hi = mid - 1;
     }
-    const uint32_t s = lo;
+    map[t] = lo;
+  }
+}
+
+// The workgroup fills `cnt` outputs of kind K from counter ctr at p
+// (element-aligned): a head up to the next 1 KiB boundary and a tail,
+// element stores, and in between chunks of B*8 16-byte vectors laid out as
+// in the plain fill (each store instruction of a wave covers one aligned KiB).
+template <int K>
+__device__ __forceinline__ void fill_range(uint64_t key, uint64_t ctr, uint64_t cnt, unsigned char* p) {
+  constexpr int W = Kind<K>::W, E = 16 / W, U = 8;
+  const uint32_t tid = threadIdx.x, B = blockDim.x;
+  const uint32_t mis = (uint32_t)((uintptr_t)p & 1023u);
+  uint64_t head = mis ? (1024u - mis) / W : 0;
+  if (head > cnt) head = cnt;
+  const uint64_t nvec = (cnt - head) / E;
+  const uint64_t tail = cnt - head - nvec * E;
+  for (uint64_t t = tid; t < head + tail; t += B) {
+    const uint64_t i = t < head ? t : head + nvec * E + (t - head);
+    store_one<K>(p + i * W, (ctr + i) * key, key);
+  }
+  u32x4* body = (u32x4*)(p + head * W);
+  const uint64_t ekey = (uint64_t)E * key;
+  const uint64_t y_body = (ctr + head) * key;
+  const uint64_t step = (uint64_t)B * ekey;
+  const uint64_t per_chunk = (uint64_t)B * U;
+#pragma unroll 1
+  for (uint64_t c0 = 0; c0 < nvec; c0 += per_chunk) {
+    const uint64_t v0 = c0 + tid;
+    uint64_t y = opaque(y_body + v0 * ekey);
+    u32x4* q = (u32x4*)opaque((uint64_t)(body + v0));
+    if (c0 + per_chunk <= nvec) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        q[(uint64_t)u * B] = gen_vec<K>(y, key);
+        y += step;
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (v0 + (uint64_t)u * B < nvec) q[(uint64_t)u * B] = gen_vec<K>(y, key);
+        y += step;
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  }
+}
+
+// Persistent: workgroup g takes tiles g, g + grid, g + 2*grid, ..., so the
+// workgroups running at any moment write neighbouring parts of the arena;
+// the stream of a tile is one load from the tile map.
+__global__ __launch_bounds__(1024) void k_batch_fill(sqi::BatchDesc d, uint32_t lg, const sqi::BatchHdr* hdr,
+                                                     const uint64_t* ts, const uint32_t* map) {
+  const uint64_t total = hdr->total_tiles;
+  const uint64_t T = 1ull << lg;
+#pragma unroll 1
+  for (uint64_t t = blockIdx.x; t < total; t += gridDim.x) {
+    const uint32_t s = map[t];
     const uint64_t off = (t - ts[s]) << lg;
     const uint64_t len = d.lens[s];
     const uint64_t cnt = len - off < T ? len - off : T;
@@ -385,8 +425,10 @@ hipError_t launch_fill(int kind, uint64_t key, uint64_t ctr0, uint64_t n, void* 
   a.key = key;
   a.ctr0 = ctr0;
   a.out = (unsigned char*)out;
-  const uint32_t mis = (uint32_t)((uintptr_t)out & 15u);
-  uint64_t head = mis ? (16u - mis) / W : 0;
+  // The body starts at a 1 KiB boundary, so each wave's 64 x 16-byte store
+  // covers exactly one aligned KiB (whole cache lines, no partial writes).
+  const uint32_t mis = (uint32_t)((uintptr_t)out & 1023u);
+  uint64_t head = mis ? (1024u - mis) / W : 0;
   if (head > n) head = n;
   a.head = (uint32_t)head;
   a.nvec = (n - head) / E;
@@ -458,8 +500,14 @@ hipError_t launch_reduce(int kind, uint64_t key, uint64_t ctr0, uint64_t n, sq_s
   return hipGetLastError();
 }
 
-size_t batch_ws_bytes(uint32_t m) {
-  const size_t b = sizeof(BatchHdr) + 8ull * ((size_t)m + 1);
+// Batch workspace: header, tile_start[m+1] (u64), tile map (u32, one per
+// tile).  Tiles are at least 2^12 outputs of at least 4 bytes, and streams
+// lie inside the arena without overlap, so there are at most
+// m + out_bytes / 2^14 tiles.
+uint64_t batch_max_tiles(uint32_t m, uint64_t out_bytes) { return (uint64_t)m + (out_bytes >> 14) + 1; }
+
+size_t batch_ws_bytes(uint32_t m, uint64_t out_bytes) {
+  const size_t b = sizeof(BatchHdr) + 8ull * ((size_t)m + 1) + 4ull * batch_max_tiles(m, out_bytes);
   return (b + 255) & ~(size_t)255;
 }
 
@@ -467,12 +515,18 @@ static hipError_t launch_batch_body(const BatchDesc& d, const uint32_t* m_dev, v
                                     hipStream_t s) {
   BatchHdr* hdr = (BatchHdr*)ws;
   uint64_t* ts = (uint64_t*)((unsigned char*)ws + sizeof(BatchHdr));
-  hipLaunchKernelGGL(k_batch_scan, dim3(1), dim3(1024), 0, s, d, m_dev, cfg.tile_log2, hdr, ts);
+  uint32_t* map = (uint32_t*)(ts + (size_t)d.m + 1);
+  const uint64_t max_tiles = batch_max_tiles(d.m, d.out_bytes);
+  hipLaunchKernelGGL(k_batch_scan, dim3(1), dim3(1024), 0, s, d, m_dev, cfg.tile_log2, max_tiles, hdr, ts);
   hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_batch_map, dim3(device_info().cus * 4), dim3(256), 0, s, (const BatchHdr*)hdr,
+                     (const uint64_t*)ts, map);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   const uint32_t grid = (uint32_t)device_info().cus * cfg.grid_per_cu;
   hipLaunchKernelGGL(k_batch_fill, dim3(grid), dim3(cfg.block), 0, s, d, cfg.tile_log2, (const BatchHdr*)hdr,
-                     (const uint64_t*)ts);
+                     (const uint64_t*)ts, (const uint32_t*)map);
   return hipGetLastError();
 }
 
@@ -481,10 +535,10 @@ hipError_t launch_batch(const BatchDesc& d, void* ws, const sq_launch_cfg& cfg, 
 }
 
 // tick ws layout: keys, ctr0s, lens, offs (u64 x max each), kinds (u8 x max,
-// padded), m (u32, padded to 256), then the batch workspace.
-size_t tick_ws_bytes(uint32_t max_entries) {
+// padded), m (u32, padded to 256), then the batch workspace over the arena.
+size_t tick_ws_bytes(uint32_t max_entries, uint64_t arena_bytes) {
   const size_t arrays = 32ull * max_entries + (((size_t)max_entries + 255) & ~(size_t)255) + 256;
-  return arrays + batch_ws_bytes(max_entries);
+  return arrays + batch_ws_bytes(max_entries, arena_bytes);
 }
 
 hipError_t launch_tick(const void* tick_buf, SlotDev* slots, uint32_t max_entries, unsigned char* arena,

@@ -332,7 +332,7 @@ int sq_server_create(const sq_server_cfg* cfg, sq_server** out) {
     e = hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&L.done, hipEventDisableTiming);
     if (e == hipSuccess) e = hipHostMalloc((void**)&L.host_buf, tbuf, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipMalloc(&L.ws, tick_ws_bytes(cfg->max_slots));
+    if (e == hipSuccess) e = hipMalloc(&L.ws, tick_ws_bytes(cfg->max_slots, cfg->hbm_budget_bytes));
     if (e != hipSuccess) break;
     ((TickHdr*)L.host_buf)->entries = 0;
     // capture expand -> scan -> fill once over this lane's fixed buffers

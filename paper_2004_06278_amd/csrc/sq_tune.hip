@@ -59,8 +59,8 @@ bool cfg_valid(sq_op op, const sq_launch_cfg& c) {
 sq_launch_cfg default_cfg(sq_op op, int kind, uint64_t n) {
   (void)n;
   switch (op) {
-    case SQ_OP_FILL: return sq_launch_cfg{1024, kind_bytes(kind) == 4 ? 8u : 4u, 16, 0, 16};
-    case SQ_OP_REDUCE: return sq_launch_cfg{256, 2, 8, 0, 16};
+    case SQ_OP_FILL: return sq_launch_cfg{256, 8, 32, 1, 16};
+    case SQ_OP_REDUCE: return sq_launch_cfg{256, 4, 8, 0, 16};
     default: return sq_launch_cfg{512, 1, 4, 0, 16};
   }
 }
@@ -166,6 +166,21 @@ static hipError_t time_best(Scratch& S, F launch, int reps, float* best_ms) {
   return hipSuccess;
 }
 
+static bool verbose() {
+  static const bool v = [] {
+    const char* e = std::getenv("SQ_TUNE_VERBOSE");
+    return e && *e && *e != '0';
+  }();
+  return v;
+}
+
+static void report(const char* op, int kind, int bucket, uint64_t n, const sq_launch_cfg& c, float ms, bool same) {
+  if (!verbose()) return;
+  std::fprintf(stderr, "tune %s kind=%d bucket=%d n=%llu block=%u unroll=%u gpc=%u xcd=%u tile=%u ms=%.4f %s\n", op,
+               kind, bucket, (unsigned long long)n, c.block, c.unroll, c.grid_per_cu, c.xcd_map, c.tile_log2, ms,
+               same ? "" : "MISMATCH");
+}
+
 static void set_entry(int op, int kind, int bucket, const sq_launch_cfg& c) {
   std::lock_guard<std::mutex> g(g_tab_mu);
   g_tab[op][kind][bucket] = Entry{c, true};
@@ -248,30 +263,29 @@ int sq_autotune(uint32_t op_mask, uint64_t max_bytes, const char* save_path) {
       const uint64_t W = kind_bytes(kind);
       for (int b = 0; b < kBuckets; ++b) {
         uint64_t n = std::min<uint64_t>(1ull << (4 * b + 15), half / W);
-        n -= 3;  // ragged: exercises the tail
+        n -= 3;  // ragged: exercises the tail (the buffers are aligned, as for timing)
         const sq_launch_cfg ref = default_cfg(SQ_OP_FILL, kind, n);
-        // outputs start 4 bytes in (a misaligned head); zero the bytes before them
-        if ((e = hipMemsetAsync(S.a, 0, 256, S.s)) != hipSuccess) break;
-        if ((e = hipMemsetAsync(S.b, 0, 256, S.s)) != hipSuccess) break;
-        if ((e = launch_fill(kind, key, ctr0, n, (unsigned char*)S.b + 4, ref, S.s)) != hipSuccess) break;
-        std::swap(S.a, S.b);  // reference now in a (at +4)
+        if ((e = launch_fill(kind, key, ctr0, n, (unsigned char*)S.b, ref, S.s)) != hipSuccess) break;
+        std::swap(S.a, S.b);  // reference now in a
         // the default is the incumbent; a candidate must beat it by 2% (timing noise)
         float best = 1e30f;
         sq_launch_cfg best_c = ref;
-        e = time_best(S, [&] { return launch_fill(kind, key, ctr0, n, (unsigned char*)S.b + 4, ref, S.s); }, 5,
+        e = time_best(S, [&] { return launch_fill(kind, key, ctr0, n, (unsigned char*)S.b, ref, S.s); }, 5,
                       &best);
         if (e != hipSuccess) break;
+        report("fill-default", kind, b, n, ref, best, true);
         for (uint32_t blk : {256u, 512u, 1024u})
           for (uint32_t u : {4u, 8u})
             for (uint32_t g : {4u, 8u, 16u, 32u})
               for (uint32_t x : {0u, 1u}) {
                 sq_launch_cfg c{blk, u, g, x, 16};
                 float ms = 0;
-                e = time_best(S, [&] { return launch_fill(kind, key, ctr0, n, (unsigned char*)S.b + 4, c, S.s); },
+                e = time_best(S, [&] { return launch_fill(kind, key, ctr0, n, (unsigned char*)S.b, c, S.s); },
                               5, &ms);
                 if (e != hipSuccess) break;
                 bool same = false;
-                if ((e = same_bytes(S, n * W + 4, &same)) != hipSuccess) break;
+                if ((e = same_bytes(S, n * W, &same)) != hipSuccess) break;
+                report("fill", kind, b, n, c, ms, same);
                 if (same && ms < 0.98f * best) { best = ms; best_c = c; }
               }
         if (e != hipSuccess) break;
@@ -294,6 +308,7 @@ int sq_autotune(uint32_t op_mask, uint64_t max_bytes, const char* save_path) {
         sq_launch_cfg best_c = ref;
         e = time_best(S, [&] { return launch_reduce(kind, key, ctr0, n, res, ws, ref, S.s); }, 5, &best);
         if (e != hipSuccess) break;
+        report("reduce-default", kind, b, n, ref, best, true);
         for (uint32_t u : {1u, 2u, 4u})
           for (uint32_t g : {2u, 4u, 8u, 16u, 32u}) {
             sq_launch_cfg c{256, u, g, 0, 16};
@@ -304,7 +319,9 @@ int sq_autotune(uint32_t op_mask, uint64_t max_bytes, const char* save_path) {
             if ((e = hipMemcpyAsync(&h[0], res, sizeof h[0], hipMemcpyDeviceToHost, S.s)) != hipSuccess) break;
             if ((e = hipMemcpyAsync(&h[1], cand, sizeof h[1], hipMemcpyDeviceToHost, S.s)) != hipSuccess) break;
             if ((e = hipStreamSynchronize(S.s)) != hipSuccess) break;
-            if (std::memcmp(&h[0], &h[1], sizeof h[0]) == 0 && ms < 0.98f * best) { best = ms; best_c = c; }
+            const bool same = std::memcmp(&h[0], &h[1], sizeof h[0]) == 0;
+            report("reduce", kind, b, n, c, ms, same);
+            if (same && ms < 0.98f * best) { best = ms; best_c = c; }
           }
         if (e == hipSuccess) set_entry(SQ_OP_REDUCE, kind, b, best_c);
       }
@@ -316,7 +333,8 @@ int sq_autotune(uint32_t op_mask, uint64_t max_bytes, const char* save_path) {
     // Synthetic ragged batches: log-uniform lengths around each bucket,
     // all four kinds, packed back to back (8-byte aligned).
     for (int b = 0; b < kBuckets && e == hipSuccess; ++b) {
-      const double lo_e = 4.0 * b + 8, hi_e = 4.0 * b + 12;
+      // bucket 2 (the one sq_fill_batch uses) spans lengths 2^10 .. 2^24
+      const double lo_e = std::max(4.0 * b + 2, 6.0), hi_e = 4.0 * b + 16;
       const uint64_t budget = half - (1ull << 20);
       std::vector<uint64_t> keys, ctrs, lens, offs;
       std::vector<uint8_t> kinds;
@@ -340,7 +358,7 @@ int sq_autotune(uint32_t op_mask, uint64_t max_bytes, const char* save_path) {
       // descriptors live in a's tail region (after the arena) in both buffers' roles:
       // the arena is [0, budget) of a/b, descriptors + workspace follow in a separate allocation
       void* desc = nullptr;
-      const size_t dbytes = 33ull * m + 64 + batch_ws_bytes(m) + 4096;
+      const size_t dbytes = 33ull * m + 64 + batch_ws_bytes(m, budget) + 4096;
       if ((e = hipMalloc(&desc, dbytes)) != hipSuccess) break;
       uint64_t* dk = (uint64_t*)desc;
       uint64_t* dc = dk + m;
@@ -362,6 +380,7 @@ int sq_autotune(uint32_t op_mask, uint64_t max_bytes, const char* save_path) {
       if (e == hipSuccess) {
         BatchDesc d{dk, dc, dl, dof, dkd, m, (unsigned char*)S.a, budget};
         e = time_best(S, [&] { return launch_batch(d, ws, ref, S.s); }, 5, &best);
+        report("batch-default", -1, b, pos, ref, best, true);
       }
       for (uint32_t tl : {14u, 16u, 18u, 20u}) {
         for (uint32_t blk : {256u, 512u, 1024u}) {
@@ -374,6 +393,7 @@ int sq_autotune(uint32_t op_mask, uint64_t max_bytes, const char* save_path) {
             if (e != hipSuccess) break;
             bool same = false;
             if ((e = same_bytes(S, used, &same)) != hipSuccess) break;
+            report("batch", -1, b, pos, c, ms, same);
             if (same && ms < 0.98f * best) { best = ms; best_c = c; }
           }
         }

@@ -82,7 +82,7 @@ SIGNATURES = {
     "sq_reduce_workspace_bytes": (ctypes.c_size_t, [_u64]),
     "sq_reduce": (_int, [_int, _u64, _u64, _u64, _vp, _vp, ctypes.c_size_t, _vp]),
     "sq_reduce_cfg": (_int, [_int, _u64, _u64, _u64, _vp, _vp, ctypes.c_size_t, ctypes.POINTER(LaunchCfg), _vp]),
-    "sq_batch_workspace_bytes": (ctypes.c_size_t, [_u32]),
+    "sq_batch_workspace_bytes": (ctypes.c_size_t, [_u32, _u64]),
     "sq_fill_batch": (_int, [_vp, _vp, _vp, _vp, _vp, _u32, _vp, _u64, _vp, ctypes.c_size_t, _vp]),
     "sq_fill_batch_cfg": (_int, [_vp, _vp, _vp, _vp, _vp, _u32, _vp, _u64, _vp, ctypes.c_size_t,
                                  ctypes.POINTER(LaunchCfg), _vp]),
@@ -280,7 +280,7 @@ def batch_to_device(keys, ctr0s, lens, offs, kinds, out_bytes: int, out=None) ->
     kd = torch.from_numpy(np.ascontiguousarray(kinds, dtype=np.uint8)).cuda()
     if out is None:
         out = torch.zeros(max(out_bytes, 16), dtype=torch.uint8, device="cuda")
-    ws = torch.empty(int(lib().sq_batch_workspace_bytes(m)), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(int(lib().sq_batch_workspace_bytes(m, out_bytes)), dtype=torch.uint8, device="cuda")
     return DeviceBatch(u64(keys), u64(ctr0s), u64(lens), u64(offs), kd, m, out, out_bytes, ws)
 
 

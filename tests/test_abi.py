@@ -46,4 +46,4 @@ def test_version_and_error_string_without_gpu():
     assert L.sq_version() >= 10000
     assert isinstance(L.sq_last_error(), bytes)
     assert L.sq_reduce_workspace_bytes(1 << 32) >= 16
-    assert L.sq_batch_workspace_bytes(4096) >= 64 + 8 * 4097
+    assert L.sq_batch_workspace_bytes(4096, 1 << 30) >= 64 + 8 * 4097 + 4 * (1 << 16)

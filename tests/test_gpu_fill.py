@@ -25,17 +25,19 @@ def sq():
 
 @pytest.mark.parametrize("kind", KINDS)
 def test_fill_small_random_misaligned(sq, oracle_mod, kind):
-    """Random keys, counters and lengths 0..5000 at every element-aligned start
-    offset inside a guarded buffer: outputs match the oracle and no byte
-    outside [start, start + n*W) changes."""
+    """Random keys, counters and lengths 0..5000 at element-aligned start
+    offsets across a KiB inside a guarded buffer: outputs match the oracle and
+    no byte outside [start, start + n*W) changes."""
     import torch
 
     g = np.random.Generator(np.random.PCG64(100 + kind))
     W = KIND_BYTES[kind]
-    buf = torch.empty(5000 * 8 + 256, dtype=torch.uint8, device="cuda")
-    for trial in range(40):
+    buf = torch.empty(5000 * 8 + 2048, dtype=torch.uint8, device="cuda")
+    for trial in range(60):
         n = int(g.integers(0, 5001)) if trial > 3 else [0, 1, 2, 3][trial]
-        off = W * int(g.integers(0, 16 // W + 2))
+        # start offsets across a whole KiB: the kernel writes a head of up to
+        # 1024/W elements one by one before its first aligned KiB
+        off = W * int(g.integers(0, 1024 // W + 2))
         key = int(g.integers(0, 2**64, dtype=np.uint64))
         ctr0 = int(g.integers(0, 2**64, dtype=np.uint64)) if trial % 3 else 2**64 - int(g.integers(1, 3000))
         log(f"fill kind={kind} trial={trial} n={n} off={off} key={key:#x} ctr0={ctr0:#x}")
