@@ -34,24 +34,32 @@ __device__ __forceinline__ uint64_t opaque(uint64_t v) {
   return v;
 }
 
-// xl*xl + a as exactly one v_mad_u64_u32 (its carry-out goes to vcc, which
-// nothing reads).  Written as a non-volatile asm statement so LLVM can still
-// schedule it, but can neither duplicate it nor, since y advances by key per
-// counter, strength-reduce round 1's y*y + y into a polynomial in the loop
-// counter (both happen with plain C).  The destination is early-clobber: it
-// must not overlap the sources.
+// The two instruction groups of a round, each pinned with a non-volatile
+// asm statement so that LLVM can schedule them but not rewrite them (with
+// plain C it duplicates the multiply-add, strength-reduces round 1's y*y + y
+// into a polynomial in the loop counter, or turns the cross term into a
+// three-instruction shift/move/multiply-add form).
+//   m  = xl*xl + a                 one v_mad_u64_u32 (carry-out to vcc, unread;
+//                                  early-clobber: dst must not overlap srcs)
+//   hi = m_hi + 2*xl*xh mod 2^32   v_mul_lo_u32 + v_lshl_add_u32
 __device__ __forceinline__ uint64_t sq_lo_plus(uint32_t xl, uint64_t a) {
   uint64_t m;
   asm("v_mad_u64_u32 %0, vcc, %1, %1, %2" : "=&v"(m) : "v"(xl), "v"(a) : "vcc");
   return m;
 }
 
+__device__ __forceinline__ uint32_t cross_add(uint32_t xl, uint32_t xh, uint32_t m_hi) {
+  uint32_t hi;
+  asm("v_mul_lo_u32 %0, %1, %2\n\tv_lshl_add_u32 %0, %0, 1, %3" : "=&v"(hi) : "v"(xl), "v"(xh), "v"(m_hi));
+  return hi;
+}
+
 // rot32(x*x + a)
 __device__ __forceinline__ uint64_t round_rot(uint64_t x, uint64_t a) {
   const uint32_t xl = (uint32_t)x, xh = (uint32_t)(x >> 32);
-  const uint64_t m = sq_lo_plus(xl, a);                           // v_mad_u64_u32
-  const uint32_t hi = (uint32_t)(m >> 32) + ((xl * xh) << 1);     // v_mul_lo_u32, v_lshl_add_u32
-  return ((uint64_t)(uint32_t)m << 32) | hi;                      // halves swapped
+  const uint64_t m = sq_lo_plus(xl, a);
+  const uint32_t hi = cross_add(xl, xh, (uint32_t)(m >> 32));
+  return ((uint64_t)(uint32_t)m << 32) | hi;  // halves swapped: no instruction
 }
 
 // x*x + a without the rotation, as (lo, hi) words
@@ -59,14 +67,14 @@ __device__ __forceinline__ void round_norot(uint64_t x, uint64_t a, uint32_t& lo
   const uint32_t xl = (uint32_t)x, xh = (uint32_t)(x >> 32);
   const uint64_t m = sq_lo_plus(xl, a);
   lo = (uint32_t)m;
-  hi = (uint32_t)(m >> 32) + ((xl * xh) << 1);
+  hi = cross_add(xl, xh, (uint32_t)(m >> 32));
 }
 
 // Upper 32 bits of x*x + a
 __device__ __forceinline__ uint32_t round_hi(uint64_t x, uint64_t a) {
   const uint32_t xl = (uint32_t)x, xh = (uint32_t)(x >> 32);
   const uint64_t m = sq_lo_plus(xl, a);
-  return (uint32_t)(m >> 32) + ((xl * xh) << 1);
+  return cross_add(xl, xh, (uint32_t)(m >> 32));
 }
 
 // squares32 from its Weyl terms y = ctr*key, z = (ctr+1)*key.

@@ -59,10 +59,10 @@ __device__ __forceinline__ void fill_chunk(const FillArgs& a, uint64_t c) {
   unsigned char* body = a.out + (uint64_t)a.head * W;
   const uint64_t v0 = c * B * U + tid;
   // opaque: otherwise loop-strength reduction keeps a separate induction
-  // variable (two VGPRs each) for every unrolled vector's y and address
+  // variable (two VGPRs each) for every unrolled vector's y
   uint64_t y = opaque(a.y_body + v0 * a.ekey);
   const uint64_t step = (uint64_t)B * a.ekey;
-  u32x4* p = (u32x4*)opaque((uint64_t)(body + v0 * 16));
+  u32x4* p = (u32x4*)(body + v0 * 16);
   if ((c + 1) * B * U <= a.nvec) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -347,7 +347,7 @@ __device__ __forceinline__ void fill_range(uint64_t key, uint64_t ctr, uint64_t 
   for (uint64_t c0 = 0; c0 < nvec; c0 += per_chunk) {
     const uint64_t v0 = c0 + tid;
     uint64_t y = opaque(y_body + v0 * ekey);
-    u32x4* q = (u32x4*)opaque((uint64_t)(body + v0));
+    u32x4* q = body + v0;
     if (c0 + per_chunk <= nvec) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
