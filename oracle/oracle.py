@@ -24,11 +24,12 @@ SRC = os.path.join(HERE, "squares_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 # Output kinds (must match the enum in squares_oracle.c).
-U32, F32, U64, F64 = 0, 1, 2, 3
-KIND_BYTES = {U32: 4, F32: 4, U64: 8, F64: 8}
-KIND_DTYPE = {U32: np.uint32, F32: np.float32, U64: np.uint64, F64: np.float64}
+U32, F32, U64, F64, U32X2, F32X2 = 0, 1, 2, 3, 4, 5
+KIND_BYTES = {U32: 4, F32: 4, U64: 8, F64: 8, U32X2: 4, F32X2: 4}
+KIND_DTYPE = {U32: np.uint32, F32: np.float32, U64: np.uint64, F64: np.float64, U32X2: np.uint32,
+              F32X2: np.float32}
 # Power-of-two scale of the integer sum of each kind: value = sum * 2^scale.
-KIND_SUM_SCALE = {U32: 0, F32: -24, U64: 0, F64: -53}
+KIND_SUM_SCALE = {U32: 0, F32: -24, U64: 0, F64: -53, U32X2: 0, F32X2: -24}
 
 
 def build(force: bool = False) -> str:
@@ -63,7 +64,8 @@ def lib() -> ctypes.CDLL:
             L.oracle_to_f32.restype = ctypes.c_float
             L.oracle_to_f64.argtypes = [u64]
             L.oracle_to_f64.restype = ctypes.c_double
-            for name in ("oracle_fill_u32", "oracle_fill_u64", "oracle_fill_f32", "oracle_fill_f64"):
+            for name in ("oracle_fill_u32", "oracle_fill_u64", "oracle_fill_f32", "oracle_fill_f64",
+                         "oracle_fill_u32x2", "oracle_fill_f32x2"):
                 fn = getattr(L, name)
                 fn.argtypes = [u64, u64, u64, vp]
                 fn.restype = None
@@ -101,7 +103,8 @@ def trace(ctr: int, key: int) -> list[int]:
 
 
 # ---------------------------------------------------------------- bulk
-_FILL = {U32: "oracle_fill_u32", F32: "oracle_fill_f32", U64: "oracle_fill_u64", F64: "oracle_fill_f64"}
+_FILL = {U32: "oracle_fill_u32", F32: "oracle_fill_f32", U64: "oracle_fill_u64", F64: "oracle_fill_f64",
+         U32X2: "oracle_fill_u32x2", F32X2: "oracle_fill_f32x2"}
 
 
 def fill(kind: int, key: int, ctr0: int, n: int, threads: int = 1) -> np.ndarray:
@@ -122,13 +125,15 @@ def fill_into(kind: int, key: int, ctr0: int, out: np.ndarray, threads: int = 1)
     if threads <= 1 or n < 4096:
         fn(key, ctr0, n, _ptr(out))
         return
-    bounds = [n * t // threads for t in range(threads + 1)]
+    # chunks start at even elements so a split kind's chunk starts at a low half
+    bounds = [(n * t // threads) & ~1 for t in range(threads)] + [n]
     width = out.itemsize
     base = _ptr(out)
+    per_ctr = 2 if kind in (U32X2, F32X2) else 1
 
     def work(t: int) -> None:
         a, b = bounds[t], bounds[t + 1]
-        fn(key, (ctr0 + a) & (2**64 - 1), b - a, base + a * width)
+        fn(key, (ctr0 + a // per_ctr) & (2**64 - 1), b - a, base + a * width)
 
     ts = [threading.Thread(target=work, args=(t,)) for t in range(threads)]
     for th in ts:
@@ -165,12 +170,13 @@ def exact_sum(kind: int, key: int, ctr0: int, n: int, threads: int = 1) -> int:
         if lib().oracle_sum(kind, key, ctr0, n, _ptr(o)) != 0:
             raise ValueError("unknown kind")
         return int(o[0]) | (int(o[1]) << 64)
-    bounds = [n * t // threads for t in range(threads + 1)]
+    bounds = [(n * t // threads) & ~1 for t in range(threads)] + [n]
     parts = [np.zeros(2, dtype=np.uint64) for _ in range(threads)]
+    per_ctr = 2 if kind in (U32X2, F32X2) else 1
 
     def work(t: int) -> None:
         a, b = bounds[t], bounds[t + 1]
-        lib().oracle_sum(kind, key, (ctr0 + a) & (2**64 - 1), b - a, _ptr(parts[t]))
+        lib().oracle_sum(kind, key, (ctr0 + a // per_ctr) & (2**64 - 1), b - a, _ptr(parts[t]))
 
     ts = [threading.Thread(target=work, args=(t,)) for t in range(threads)]
     for th in ts:

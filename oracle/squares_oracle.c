@@ -131,8 +131,31 @@ double oracle_to_f64(uint64_t u)
  * ------------------------------------------------------------------------ */
 
 /* Output kinds shared with the tests (values are part of the test contract,
- * not taken from any other code). */
-enum { ORACLE_U32 = 0, ORACLE_F32 = 1, ORACLE_U64 = 2, ORACLE_F64 = 3 };
+ * not taken from any other code).  U32X2 / F32X2 split each squares64 output
+ * into two 32-bit outputs (Section 5 reports timing this split): element i
+ * comes from counter ctr0 + i/2, the low half for even i and the high half for
+ * odd i (the little-endian order of the 64-bit output in memory); F32X2
+ * converts each half like F32. */
+enum { ORACLE_U32 = 0, ORACLE_F32 = 1, ORACLE_U64 = 2, ORACLE_F64 = 3, ORACLE_U32X2 = 4, ORACLE_F32X2 = 5 };
+
+/* The 32-bit half of squares64 that split element i uses. */
+static uint32_t split_half(uint64_t key, uint64_t ctr0, uint64_t i)
+{
+    const uint64_t v = oracle_squares64(ctr0 + i / 2, key);
+    return (i % 2 == 0) ? (uint32_t)v : (uint32_t)(v >> 32);
+}
+
+void oracle_fill_u32x2(uint64_t key, uint64_t ctr0, uint64_t n, uint32_t *out)
+{
+    for (uint64_t i = 0; i < n; ++i)
+        out[i] = split_half(key, ctr0, i);
+}
+
+void oracle_fill_f32x2(uint64_t key, uint64_t ctr0, uint64_t n, float *out)
+{
+    for (uint64_t i = 0; i < n; ++i)
+        out[i] = oracle_to_f32(split_half(key, ctr0, i));
+}
 
 void oracle_fill_u32(uint64_t key, uint64_t ctr0, uint64_t n, uint32_t *out)
 {
@@ -162,7 +185,7 @@ void oracle_fill_f64(uint64_t key, uint64_t ctr0, uint64_t n, double *out)
 int oracle_kind_bytes(int kind)
 {
     switch (kind) {
-    case ORACLE_U32: case ORACLE_F32: return 4;
+    case ORACLE_U32: case ORACLE_F32: case ORACLE_U32X2: case ORACLE_F32X2: return 4;
     case ORACLE_U64: case ORACLE_F64: return 8;
     default: return 0;
     }
@@ -179,6 +202,8 @@ static int fill_kind(int kind, uint64_t key, uint64_t ctr0, uint64_t n,
         case ORACLE_F32: { float v = oracle_to_f32(oracle_squares32(c, key)); memcpy(dst + 4 * i, &v, 4); break; }
         case ORACLE_U64: { uint64_t v = oracle_squares64(c, key); memcpy(dst + 8 * i, &v, 8); break; }
         case ORACLE_F64: { double v = oracle_to_f64(oracle_squares64(c, key)); memcpy(dst + 8 * i, &v, 8); break; }
+        case ORACLE_U32X2: { uint32_t v = split_half(key, ctr0, i); memcpy(dst + 4 * i, &v, 4); break; }
+        case ORACLE_F32X2: { float v = oracle_to_f32(split_half(key, ctr0, i)); memcpy(dst + 4 * i, &v, 4); break; }
         default: return -1;
         }
     }
@@ -204,6 +229,7 @@ int oracle_fill_batch(uint32_t m, const uint64_t *keys, const uint64_t *ctr0s,
  * the integers whose scaled values are the outputs:
  *   U32: squares32          F32: squares32 >> 8   (value = sum * 2^-24)
  *   U64: squares64          F64: squares64 >> 11  (value = sum * 2^-53)
+ *   U32X2: each split half  F32X2: each split half >> 8 (value = sum * 2^-24)
  * as an exact 128-bit integer, so it does not depend on summation order.
  * out[0] = low 64 bits, out[1] = high 64 bits.  Returns 0, or -1 on an
  * unknown kind.
@@ -218,6 +244,8 @@ int oracle_sum(int kind, uint64_t key, uint64_t ctr0, uint64_t n, uint64_t out[2
         case ORACLE_F32: acc += oracle_squares32(c, key) >> 8; break;
         case ORACLE_U64: acc += oracle_squares64(c, key); break;
         case ORACLE_F64: acc += oracle_squares64(c, key) >> 11; break;
+        case ORACLE_U32X2: acc += split_half(key, ctr0, i); break;
+        case ORACLE_F32X2: acc += split_half(key, ctr0, i) >> 8; break;
         default: return -1;
         }
     }

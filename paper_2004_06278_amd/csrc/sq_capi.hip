@@ -184,6 +184,8 @@ int sq_fill_batch_cfg(const uint64_t* keys, const uint64_t* ctr0s, const uint64_
 int sq_fill_batch(const uint64_t* keys, const uint64_t* ctr0s, const uint64_t* lens, const uint64_t* offs,
                   const uint8_t* kinds, uint32_t m, void* out, uint64_t out_bytes, void* ws, size_t ws_bytes,
                   void* stream) {
+  int rc = check_batch(keys, ctr0s, lens, offs, kinds, m, out, out_bytes, ws, ws_bytes);
+  if (rc != SQ_OK || m == 0) return rc;
   SQ_INIT_OR_RETURN();
   const sq_launch_cfg cfg = tuned_cfg(SQ_OP_BATCH, SQ_U32, mean_bucket_len(m));
   return sq_fill_batch_cfg(keys, ctr0s, lens, offs, kinds, m, out, out_bytes, ws, ws_bytes, &cfg, stream);
@@ -193,14 +195,15 @@ int sq_fill_streams(const uint64_t* keys, const uint64_t* ctr0s, const uint64_t*
                     const uint8_t* kinds, uint32_t m, void* out, uint64_t out_bytes, void* stream) {
   if (m == 0) return SQ_OK;
   if (!keys || !ctr0s || !lens || !offs || !kinds || !out) return fail(SQ_EINVAL, "null host descriptor or arena");
-  SQ_INIT_OR_RETURN();
   for (uint32_t s = 0; s < m; ++s) {
     const int W = kind_bytes(kinds[s]);
     if (W == 0) return fail(SQ_EINVAL, "stream " + std::to_string(s) + ": unknown kind");
-    if (offs[s] % W != 0) return fail(SQ_EALIGN, "stream " + std::to_string(s) + ": misaligned offset");
+    if (offs[s] % W != 0 || ((uintptr_t)out & (uintptr_t)(W - 1)) != 0)
+      return fail(SQ_EALIGN, "stream " + std::to_string(s) + ": misaligned offset");
     if (offs[s] > out_bytes || lens[s] > (out_bytes - offs[s]) / W)
       return fail(SQ_EINVAL, "stream " + std::to_string(s) + ": range past the arena");
   }
+  SQ_INIT_OR_RETURN();
   for (uint32_t s = 0; s < m; ++s) {
     if (lens[s] == 0) continue;
     const sq_launch_cfg cfg = tuned_cfg(SQ_OP_FILL, kinds[s], lens[s]);

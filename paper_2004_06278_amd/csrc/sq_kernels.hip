@@ -158,20 +158,34 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a) {
   uint64_t y = (a.ctr0 + t * a.per) * key;
   uint64_t lo = 0, hi = 0;
   if constexpr (K == 2) {
-    // 64-bit terms: carry into the high word after every term
+    // 64-bit terms: a 64-bit partial plus a 32-bit count of its carries,
+    // folded into the 128-bit total every 2^20 terms
     uint64_t i = 0;
-    for (; i + U <= cnt; i += U) {
+    while (i < cnt) {
+      const uint64_t len = cnt - i < (1u << 20) ? cnt - i : (1u << 20);
+      uint64_t s = 0;
+      uint32_t carries = 0;
+      uint64_t j = 0;
+      for (; j + U <= len; j += U) {
+        y = opaque(y);
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
+        for (int u = 0; u < U; ++u) {
+          const uint64_t z = y + key;
+          unsigned long long c;
+          s = __builtin_addcll(s, sum_term<K>(y, z), 0ull, &c);
+          carries += (uint32_t)c;
+          y = z;
+        }
+      }
+      for (; j < len; ++j) {
         const uint64_t z = y + key;
-        add128(lo, hi, sum_term<K>(y, z), 0);
+        unsigned long long c;
+        s = __builtin_addcll(s, sum_term<K>(y, z), 0ull, &c);
+        carries += (uint32_t)c;
         y = z;
       }
-    }
-    for (; i < cnt; ++i) {
-      const uint64_t z = y + key;
-      add128(lo, hi, sum_term<K>(y, z), 0);
-      y = z;
+      add128(lo, hi, s, carries);
+      i += len;
     }
   } else {
     // Terms < 2^53 (F64) and < 2^32 (U32) go into a 64-bit partial that is
@@ -185,6 +199,10 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a) {
       Part s = 0;
       uint64_t j = 0;
       for (; j + U <= len; j += U) {
+        // opaque: otherwise loop-strength reduction rewrites every unrolled
+        // y as base + (j+u)*key with its own induction variable, plus a
+        // separate 32-bit add for its low word
+        y = opaque(y);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const uint64_t z = y + key;

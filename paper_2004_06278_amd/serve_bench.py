@@ -89,7 +89,7 @@ def run_short(sq, torch, budget: int = 32 << 30, chunk_cap: int = 1 << 24) -> di
     cap_trace = W.serve_trace(seed=5, r=2000, qps=1e9)
     cap = saturated(sq, cap_trace, budget, chunk_cap)
     qps = 0.5 * cap["req_per_s"]
-    tr = W.serve_trace(seed=6, r=6000, qps=qps)
+    tr = W.serve_trace(seed=6, r=21000, qps=qps)
     ol = open_loop(sq, tr, budget, chunk_cap, warmup=1000)
     torch.cuda.synchronize()
     return {"workload": "Poisson arrivals, sizes log-uniform 2^10..2^28 outputs, 70% 32-bit / 30% 64-bit",

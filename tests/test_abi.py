@@ -47,3 +47,137 @@ def test_version_and_error_string_without_gpu():
     assert isinstance(L.sq_last_error(), bytes)
     assert L.sq_reduce_workspace_bytes(1 << 32) >= 16
     assert L.sq_batch_workspace_bytes(4096, 1 << 30) >= 64 + 8 * 4097 + 4 * (1 << 16)
+
+
+# ---------------------------------------------------------------- host-side validation (no GPU needed)
+# Every call below is rejected by argument checks that run before the library
+# touches a device, so the status codes are the same with or without a GPU.
+# Device pointers are plain integers here; nothing dereferences them.
+FAKE = 1 << 40  # 1 KiB-aligned stand-in address
+
+
+def _rc(fn, *args):
+    from paper_2004_06278_amd import squares
+
+    return fn(*args), squares.lib().sq_last_error().decode()
+
+
+def test_fill_argument_checks():
+    from paper_2004_06278_amd import squares
+
+    L = squares.lib()
+    rc, msg = _rc(L.sq_fill, 9, 1, 0, 10, FAKE, None)
+    assert rc == -1 and "kind" in msg
+    rc, _ = _rc(L.sq_fill, 0, 1, 0, 10, FAKE + 2, None)
+    assert rc == -2
+    rc, _ = _rc(L.sq_fill, 2, 1, 0, 10, FAKE + 4, None)
+    assert rc == -2
+    rc, _ = _rc(L.sq_fill, 0, 1, 0, 10, None, None)
+    assert rc == -1
+    assert L.sq_fill(0, 1, 0, 0, None, None) == 0          # n == 0: nothing to do
+    assert L.sq32_fill(1, 0, 0, None, None) == 0
+    bad = squares.LaunchCfg(128, 8, 16, 0, 16)
+    rc, _ = _rc(L.sq_fill_cfg, 0, 1, 0, 10, FAKE, bad, None)
+    assert rc == -1
+    bad = squares.LaunchCfg(256, 3, 16, 0, 16)             # unroll must be 4 or 8
+    rc, _ = _rc(L.sq_fill_cfg, 0, 1, 0, 10, FAKE, bad, None)
+    assert rc == -1
+
+
+def test_reduce_argument_checks():
+    from paper_2004_06278_amd import squares
+
+    L = squares.lib()
+    need = L.sq_reduce_workspace_bytes(1 << 20)
+    good = squares.LaunchCfg(256, 4, 8, 0, 16)
+    assert _rc(L.sq_reduce_cfg, 7, 1, 0, 10, FAKE, FAKE, need, good, None)[0] == -1
+    assert _rc(L.sq_reduce_cfg, 1, 1, 0, 10, None, FAKE, need, good, None)[0] == -1
+    assert _rc(L.sq_reduce_cfg, 1, 1, 0, 10, FAKE + 4, FAKE, need, good, None)[0] == -2
+    assert _rc(L.sq_reduce_cfg, 1, 1, 0, 10, FAKE, FAKE + 8, need, good, None)[0] == -2
+    assert _rc(L.sq_reduce_cfg, 1, 1, 0, 10, FAKE, FAKE, need - 16, good, None)[0] == -3
+    assert _rc(L.sq_reduce_cfg, 1, 1, 0, 10, FAKE, FAKE, need, squares.LaunchCfg(256, 3, 8, 0, 16), None)[0] == -1
+
+
+def test_batch_argument_checks():
+    from paper_2004_06278_amd import squares
+
+    L = squares.lib()
+    m, arena = 8, 1 << 20
+    ws = L.sq_batch_workspace_bytes(m, arena)
+    args = [FAKE, FAKE, FAKE, FAKE, FAKE, m, FAKE, arena, FAKE, ws, None]
+    assert L.sq_fill_batch(*(args[:5] + [0] + args[6:])) == 0   # m == 0
+    a = list(args); a[0] = None
+    assert _rc(L.sq_fill_batch, *a)[0] == -1
+    a = list(args); a[1] = FAKE + 4
+    assert _rc(L.sq_fill_batch, *a)[0] == -2
+    a = list(args); a[6] = FAKE + 4
+    assert _rc(L.sq_fill_batch, *a)[0] == -2
+    a = list(args); a[9] = ws - 256
+    assert _rc(L.sq_fill_batch, *a)[0] == -3
+    assert L.sq_batch_workspace_bytes(m, 2 * arena) > ws       # the tile map grows with the arena
+
+
+def test_per_stream_host_checks():
+    import numpy as np
+
+    from paper_2004_06278_amd import squares
+
+    L = squares.lib()
+    keys = np.ones(3, dtype=np.uint64)
+    ctrs = np.zeros(3, dtype=np.uint64)
+    lens = np.array([10, 10, 10], dtype=np.uint64)
+    offs = np.array([0, 64, 128], dtype=np.uint64)
+
+    def call(kinds, offs_=offs, lens_=lens, arena=1024):
+        kd = np.asarray(kinds, dtype=np.uint8)
+        return L.sq_fill_streams(keys.ctypes.data, ctrs.ctypes.data, lens_.ctypes.data, offs_.ctypes.data,
+                                 kd.ctypes.data, 3, FAKE, arena, None)
+
+    assert call([0, 9, 1]) == -1                                  # unknown kind
+    assert call([0, 2, 1], offs_=np.array([0, 68, 128], dtype=np.uint64)) == -2  # u64 stream at 68
+    assert call([0, 0, 0], arena=100) == -1                       # past the arena
+
+
+def test_server_argument_checks():
+    from paper_2004_06278_amd import squares
+
+    L = squares.lib()
+    h = squares.ctypes.c_void_p()
+    for cfg in (squares.ServerCfg(100, 4, 4096, 2, 0),          # budget too small
+                squares.ServerCfg(1 << 20, 0, 4096, 2, 0),      # no slots
+                squares.ServerCfg(1 << 20, 4, 100, 2, 0),       # chunk too small
+                squares.ServerCfg(1 << 20, 4, 4096, 9, 0),      # too many streams
+                squares.ServerCfg(1 << 20, 4, 4096, 2, 30)):    # tile out of range
+        assert L.sq_server_create(squares.ctypes.byref(cfg), squares.ctypes.byref(h)) == -1
+    rid = squares.ctypes.c_uint64()
+    assert L.sq_server_submit(None, 0, 1, 0, 10, 0, squares.ctypes.byref(rid)) == -1
+    assert L.sq_server_destroy(None) == 0
+
+
+def test_tune_table_roundtrip(tmp_path):
+    """The tuning table is host state: set, get, save and load without a GPU."""
+    from paper_2004_06278_amd import squares
+
+    L = squares.lib()
+    c = squares.LaunchCfg(512, 4, 12, 1, 16)
+    assert L.sq_tune_set(0, 2, 1 << 22, squares.ctypes.byref(c)) == 0
+    got = squares.LaunchCfg()
+    assert L.sq_tune_get(0, 2, (1 << 22) + 5, squares.ctypes.byref(got)) == 0   # same size bucket
+    assert got.as_dict() == c.as_dict()
+    path = str(tmp_path / "table.json")
+    assert L.sq_tune_save(path.encode()) == 0
+    import json
+
+    rows = json.load(open(path))
+    assert any(r["op"] == 0 and r["kind"] == 2 and r["bucket"] == 2 and r["block"] == 512 for r in rows)
+    other = squares.LaunchCfg(1024, 8, 3, 0, 16)
+    assert L.sq_tune_set(0, 2, 1 << 22, squares.ctypes.byref(other)) == 0
+    assert L.sq_tune_load(path.encode()) == 0
+    assert L.sq_tune_get(0, 2, 1 << 22, squares.ctypes.byref(got)) == 0
+    assert got.as_dict() == c.as_dict()
+    bad = squares.LaunchCfg(100, 4, 12, 1, 16)
+    assert L.sq_tune_set(0, 2, 1 << 22, squares.ctypes.byref(bad)) == -1
+    assert L.sq_tune_load(b"/nonexistent/table.json") == -6
+    # restore the shipped table for later tests in this process
+    if os.path.exists(squares.TUNE_TABLE):
+        assert L.sq_tune_load(squares.TUNE_TABLE.encode()) == 0

@@ -339,3 +339,55 @@ def test_config1_oracle_under_one_second(oracle_mod):
         dt.append(time.perf_counter() - t0)
     assert min(dt) < 1.0, dt
     assert not balance_screen(u, 32)
+
+
+# ---------------------------------------------------------------- split squares64 (two 32-bit outputs per call)
+def test_split_halves_are_squares64_words(oracle_mod):
+    """Split element 2j is the low word and 2j+1 the high word of squares64 at
+    ctr0+j (Section 5's split into two 32-bit halves, read in little-endian
+    order): the split fill is the 64-bit fill's memory viewed as 32-bit words."""
+    o = oracle_mod
+    key, ctr0 = 0x9D2C5680A1B3E7F4, 2**64 - 37
+    for n in (0, 1, 2, 77, 1000):
+        a = o.fill(o.U32X2, key, ctr0, n)
+        b = o.fill(o.U64, key, ctr0, (n + 1) // 2).view(np.uint32)[:n]
+        assert a.tobytes() == b.tobytes()
+
+
+def test_split_high_words_are_squares32(oracle_mod):
+    """The odd (high-word) split outputs equal squares32 at the same counter,
+    because squares64 keeps round 4 whole and only XORs below 2^32."""
+    o = oracle_mod
+    key, ctr0, n = 0x0F7E6D5C4B3A2918, 123456789, 4096
+    a = o.fill(o.U32X2, key, ctr0, 2 * n)
+    assert np.array_equal(a[1::2], o.fill(o.U32, key, ctr0, n))
+
+
+def test_split_floats_top_24_bits(oracle_mod):
+    o = oracle_mod
+    key, ctr0, n = 0x7C3B9A1E5D2F4068, 5, 1 << 14
+    u = o.fill(o.U32X2, key, ctr0, n).astype(np.float64)
+    f = o.fill(o.F32X2, key, ctr0, n).astype(np.float64)
+    assert np.all(f * 2**24 == np.floor(f * 2**24))
+    d = u * 2.0**-32 - f
+    assert np.all(d >= 0) and np.all(d < 2.0**-24)
+
+
+@pytest.mark.parametrize("kind", [4, 5])
+def test_split_sums_and_wrap(oracle_mod, kind):
+    o = oracle_mod
+    key, ctr0 = 0x2E4A6C8E0B1D3F57, 2**64 - 1000
+    n = 20001
+    vals = o.fill(o.U32X2, key, ctr0, n).astype(object)
+    shift = 8 if kind == 5 else 0
+    expect = sum(int(v) >> shift for v in vals)
+    assert o.exact_sum(kind, key, ctr0, n) == expect
+    assert o.exact_sum(kind, key, ctr0, n, threads=7) == expect
+    for b in (0, 2, 1998, 2000, 20000):  # even split points: the second part starts at a low word
+        left = o.exact_sum(kind, key, ctr0, b)
+        right = o.exact_sum(kind, key, (ctr0 + b // 2) % 2**64, n - b)
+        assert left + right == expect
+    # the counter wraps after 1000 calls = 2000 split outputs
+    whole = o.fill(kind, key, ctr0, n)
+    parts = np.concatenate([o.fill(kind, key, ctr0, 2000), o.fill(kind, key, 0, n - 2000)])
+    assert whole.tobytes() == parts.tobytes()
