@@ -12,8 +12,9 @@ steps with a device synchronisation on both sides; inputs are scalars, so
 nothing is transferred.  The JSON line carries the whole-step rate, each
 kernel's average duration from HIP events on the launch stream, the
 roofline of the dominant kernel, the CPU oracle's rate on a bounded sample,
-and (unless --no-extras) the ragged-batch speedup over per-stream launches
-and serving latency percentiles.
+and (unless --no-extras) the split-word variant of squares64, the
+ragged-batch speedup over per-stream launches and serving latency
+percentiles.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--log2n 32] [--no-extras]
 """
@@ -171,6 +172,35 @@ def batch_speedup(sq, torch) -> dict:
             "speedup": round(t_each / t_plan, 2)}
 
 
+def split_words(sq, torch, key: int, ctr0: int, n: int, per_op_ms: dict) -> dict:
+    """squares64 split into two 32-bit outputs per call (Section 5): a 2^32-output
+    U32X2 fill and F32X2 fused sum, timed like the step kernels (mean of 10
+    after 2 warm-up), beside the squares32 fill and F32 sum of the step."""
+    out = torch.empty(n, dtype=torch.uint32, device="cuda")
+    res, ws = sq.result_tensor(), sq.reduce_workspace(n)
+    ops = {"u32x2_fill": lambda: sq.fill(sq.U32X2, key, ctr0, n, out=out),
+           "fused_f32x2_sum": lambda: sq.reduce_async(sq.F32X2, key, ctr0, n, res, ws)}
+    r = {}
+    for name, fn in ops.items():
+        for _ in range(2):
+            fn()
+        evs = []
+        for _ in range(10):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            evs.append((a, b))
+        torch.cuda.synchronize()
+        ms = sum(a.elapsed_time(b) for a, b in evs) / len(evs)
+        r[name] = {"ms": round(ms, 4), "gnum_s": round(n / (ms * 1e-3) / 1e9, 1)}
+    r["u32x2_fill"]["vs_sq32_fill"] = round(per_op_ms["sq32_fill"] / r["u32x2_fill"]["ms"], 3)
+    r["fused_f32x2_sum"]["vs_fused_f32_sum"] = round(per_op_ms["fused_f32_sum"] / r["fused_f32x2_sum"]["ms"], 3)
+    del out
+    torch.cuda.empty_cache()
+    return r
+
+
 def main() -> int:
     args = parse()
     if args.traffic:
@@ -307,6 +337,7 @@ def main() -> int:
     del out32, out64
     torch.cuda.empty_cache()
     if not args.no_extras:
+        line["split_words"] = split_words(sq, torch, key, ctr0, n, per_op_ms)
         line["batch"] = batch_speedup(sq, torch)
         try:
             from paper_2004_06278_amd import serve_bench

@@ -45,8 +45,14 @@ extern "C" {
  * F32 = (squares32 >> 8) * 2^-24 and F64 = (squares64 >> 11) * 2^-53: the
  * paper reports 32-bit and 53-bit precision floating point outputs
  * (Section 5) without a formula; these take the top 24 / 53 bits, which
- * converts exactly into [0, 1). */
-typedef enum { SQ_U32 = 0, SQ_F32 = 1, SQ_U64 = 2, SQ_F64 = 3 } sq_kind;
+ * converts exactly into [0, 1).
+ * U32X2/F32X2 split each squares64 output into two 32-bit outputs, which
+ * Section 5 reports as faster per 32-bit output than squares32: element i
+ * comes from counter ctr0 + i/2, the low word for even i and the high word
+ * for odd i (the 64-bit output's little-endian order in memory); F32X2
+ * converts each word like F32.  Output pointers and batch offsets of the
+ * 8-byte kinds and of the split kinds must be 8-byte aligned. */
+typedef enum { SQ_U32 = 0, SQ_F32 = 1, SQ_U64 = 2, SQ_F64 = 3, SQ_U32X2 = 4, SQ_F32X2 = 5 } sq_kind;
 
 typedef enum {
     SQ_OK = 0,
@@ -72,9 +78,10 @@ int sq_init(void);
 /* ------------------------------------------------------------------------
  * Bulk fills over a counter range (Section 2 squares32, Section 5 squares64).
  *   out[i] = f(ctr0 + i mod 2^64, key),  i in [0, n)
- * `out` must be aligned to the element size (4 or 8 bytes), else SQ_EALIGN;
- * 16-byte alignment is not required (a misaligned head and tail are
- * written element by element).  n == 0 returns SQ_OK without a launch; a
+ * `out` must be aligned to 4 bytes (U32, F32) or 8 bytes (other kinds), else
+ * SQ_EALIGN; 16-byte alignment is not required (elements up to the first
+ * 1 KiB boundary and after the last full 16-byte vector are written one by
+ * one).  n == 0 returns SQ_OK without a launch; a
  * null `out` with n > 0 is SQ_EINVAL.  out must hold n elements.
  * ------------------------------------------------------------------------ */
 int sq32_fill(uint64_t key, uint64_t ctr0, uint64_t n, uint32_t *out, void *stream);
@@ -84,6 +91,9 @@ int sq_uniform_f32(uint64_t key, uint64_t ctr0, uint64_t n, float *out, void *st
 int sq_uniform_f64(uint64_t key, uint64_t ctr0, uint64_t n, double *out, void *stream);
 /* The four fills above behind one kind argument. */
 int sq_fill(sq_kind kind, uint64_t key, uint64_t ctr0, uint64_t n, void *out, void *stream);
+/* The split kinds by name: out[i] = 32-bit word (i & 1) of squares64(ctr0 + i/2). */
+int sq64x2_fill(uint64_t key, uint64_t ctr0, uint64_t n, uint32_t *out, void *stream);
+int sq_uniform_f32x2(uint64_t key, uint64_t ctr0, uint64_t n, float *out, void *stream);
 
 /* ------------------------------------------------------------------------
  * Launch configurations (chosen by the autotuner; explicit for tests).
@@ -127,6 +137,8 @@ int sq_autotune(uint32_t op_mask, uint64_t max_bytes, const char *save_path);
  * The sum is of the integers whose scaled values are the outputs:
  *   SQ_U32: squares32        SQ_F32: squares32 >> 8   (value = sum * 2^-24)
  *   SQ_U64: squares64        SQ_F64: squares64 >> 11  (value = sum * 2^-53)
+ *   SQ_U32X2: each word      SQ_F32X2: each word >> 8 (value = sum * 2^-24)
+ * over the same n outputs a fill of that kind would write.
  * as an exact 128-bit integer, so the result does not depend on the order of
  * summation or on the launch configuration.  `value` is that sum times the
  * kind's scale rounded to the nearest double (ties to even).
@@ -222,6 +234,7 @@ typedef struct {
 
 /* submit() flags */
 #define SQ_SERVE_DISCARD 1u     /* free the output as soon as the request completes */
+#define SQ_SERVE_NO_STATS 2u    /* leave this request out of the latency statistics (warm-up) */
 
 typedef struct {
     uint64_t submitted, admitted, completed, released;

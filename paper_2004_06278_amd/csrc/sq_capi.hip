@@ -78,12 +78,12 @@ int sq_init(void) {
 
 // ---------------------------------------------------------------- fills
 static int check_fill(int kind, uint64_t n, const void* out) {
-  const int W = kind_bytes(kind);
-  if (W == 0) return fail(SQ_EINVAL, "unknown kind " + std::to_string(kind));
+  const int A = kind_align(kind);
+  if (A == 0) return fail(SQ_EINVAL, "unknown kind " + std::to_string(kind));
   if (n == 0) return SQ_OK;
   if (out == nullptr) return fail(SQ_EINVAL, "null output pointer with n > 0");
-  if (((uintptr_t)out & (uintptr_t)(W - 1)) != 0)
-    return fail(SQ_EALIGN, "output pointer not aligned to " + std::to_string(W) + " bytes");
+  if (((uintptr_t)out & (uintptr_t)(A - 1)) != 0)
+    return fail(SQ_EALIGN, "output pointer not aligned to " + std::to_string(A) + " bytes");
   return SQ_OK;
 }
 
@@ -117,6 +117,12 @@ int sq_uniform_f32(uint64_t key, uint64_t ctr0, uint64_t n, float* out, void* st
 }
 int sq_uniform_f64(uint64_t key, uint64_t ctr0, uint64_t n, double* out, void* stream) {
   return sq_fill(SQ_F64, key, ctr0, n, out, stream);
+}
+int sq64x2_fill(uint64_t key, uint64_t ctr0, uint64_t n, uint32_t* out, void* stream) {
+  return sq_fill(SQ_U32X2, key, ctr0, n, out, stream);
+}
+int sq_uniform_f32x2(uint64_t key, uint64_t ctr0, uint64_t n, float* out, void* stream) {
+  return sq_fill(SQ_F32X2, key, ctr0, n, out, stream);
 }
 
 // ---------------------------------------------------------------- reduce
@@ -196,9 +202,9 @@ int sq_fill_streams(const uint64_t* keys, const uint64_t* ctr0s, const uint64_t*
   if (m == 0) return SQ_OK;
   if (!keys || !ctr0s || !lens || !offs || !kinds || !out) return fail(SQ_EINVAL, "null host descriptor or arena");
   for (uint32_t s = 0; s < m; ++s) {
-    const int W = kind_bytes(kinds[s]);
+    const int W = kind_bytes(kinds[s]), A = kind_align(kinds[s]);
     if (W == 0) return fail(SQ_EINVAL, "stream " + std::to_string(s) + ": unknown kind");
-    if (offs[s] % W != 0 || ((uintptr_t)out & (uintptr_t)(W - 1)) != 0)
+    if (offs[s] % A != 0 || ((uintptr_t)out & (uintptr_t)(A - 1)) != 0)
       return fail(SQ_EALIGN, "stream " + std::to_string(s) + ": misaligned offset");
     if (offs[s] > out_bytes || lens[s] > (out_bytes - offs[s]) / W)
       return fail(SQ_EINVAL, "stream " + std::to_string(s) + ": range past the arena");

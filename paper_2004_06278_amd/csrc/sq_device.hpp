@@ -104,14 +104,19 @@ __device__ __forceinline__ float to_f32(uint32_t u) { return (float)(u >> 8) * 0
 __device__ __forceinline__ double to_f64(uint64_t u) { return (double)(u >> 11) * 0x1p-53; }
 
 // Output-kind traits.  Kind numbering matches sq_kind in squares.h.
+//   W:     bytes per output element
+//   CPV:   counters consumed by one 16-byte vector of outputs
+//   SPLIT: each squares64 output gives two 32-bit elements (low word first)
 template <int K> struct Kind;
-template <> struct Kind<0> { static constexpr int W = 4; };  // U32
-template <> struct Kind<1> { static constexpr int W = 4; };  // F32
-template <> struct Kind<2> { static constexpr int W = 8; };  // U64
-template <> struct Kind<3> { static constexpr int W = 8; };  // F64
+template <> struct Kind<0> { static constexpr int W = 4, CPV = 4; static constexpr bool SPLIT = false; };  // U32
+template <> struct Kind<1> { static constexpr int W = 4, CPV = 4; static constexpr bool SPLIT = false; };  // F32
+template <> struct Kind<2> { static constexpr int W = 8, CPV = 2; static constexpr bool SPLIT = false; };  // U64
+template <> struct Kind<3> { static constexpr int W = 8, CPV = 2; static constexpr bool SPLIT = false; };  // F64
+template <> struct Kind<4> { static constexpr int W = 4, CPV = 2; static constexpr bool SPLIT = true; };   // U32X2
+template <> struct Kind<5> { static constexpr int W = 4, CPV = 2; static constexpr bool SPLIT = true; };   // F32X2
 
-// One output of kind K for the counter whose Weyl terms are (y, z), as raw
-// bits (low word first for 8-byte kinds).
+// One output of non-split kind K for the counter whose Weyl terms are
+// (y, z), as raw bits (low word first for 8-byte kinds).
 template <int K>
 __device__ __forceinline__ uint64_t gen_bits(uint64_t y, uint64_t z) {
   if constexpr (K == 0) return sq32(y, z);
@@ -120,12 +125,31 @@ __device__ __forceinline__ uint64_t gen_bits(uint64_t y, uint64_t z) {
   if constexpr (K == 3) return (uint64_t)__double_as_longlong(to_f64(sq64(y, z)));
 }
 
+// Both 32-bit elements of a split kind from one squares64 output.
+template <int K>
+__device__ __forceinline__ void split_pair(uint64_t y, uint64_t z, uint32_t& lo, uint32_t& hi) {
+  const uint64_t v = sq64(y, z);
+  lo = (uint32_t)v;
+  hi = (uint32_t)(v >> 32);
+  if constexpr (K == 5) {
+    lo = __float_as_uint(to_f32(lo));
+    hi = __float_as_uint(to_f32(hi));
+  }
+}
+
 // Sixteen bytes of consecutive outputs starting at the counter with first
-// Weyl term y0: four 32-bit outputs or two 64-bit outputs.
+// Weyl term y0: four 32-bit outputs (squares32, or two split squares64
+// outputs) or two 64-bit outputs.
 template <int K>
 __device__ __forceinline__ u32x4 gen_vec(uint64_t y0, uint64_t key) {
   u32x4 o;
-  if constexpr (Kind<K>::W == 4) {
+  if constexpr (Kind<K>::SPLIT) {
+    const uint64_t y1 = y0 + key, y2 = y1 + key;
+    uint32_t a, b, c, d;
+    split_pair<K>(y0, y1, a, b);
+    split_pair<K>(y1, y2, c, d);
+    o.x = a; o.y = b; o.z = c; o.w = d;
+  } else if constexpr (Kind<K>::W == 4) {
     const uint64_t y1 = y0 + key, y2 = y1 + key, y3 = y2 + key, y4 = y3 + key;
     o.x = (uint32_t)gen_bits<K>(y0, y1);
     o.y = (uint32_t)gen_bits<K>(y1, y2);
@@ -140,22 +164,53 @@ __device__ __forceinline__ u32x4 gen_vec(uint64_t y0, uint64_t key) {
   return o;
 }
 
-// Writes one output of kind K (element store, for heads and tails).
+// Counter offset of element i of a range (split kinds: two elements per
+// counter).
 template <int K>
-__device__ __forceinline__ void store_one(unsigned char* p, uint64_t y, uint64_t key) {
-  const uint64_t v = gen_bits<K>(y, y + key);
-  if constexpr (Kind<K>::W == 4) *(uint32_t*)p = (uint32_t)v;
-  else *(uint64_t*)p = v;
+__device__ __forceinline__ uint64_t elem_ctr(uint64_t i) {
+  return Kind<K>::SPLIT ? i >> 1 : i;
 }
 
-// The integer a reduce of kind K sums for one output (the value is that
-// integer times 2^-24 for F32 and 2^-53 for F64).
+// Writes element i of a range that starts at counter ctr0 (element store,
+// for heads and tails); p is the element's address.
+template <int K>
+__device__ __forceinline__ void store_elem(unsigned char* p, uint64_t ctr0, uint64_t i, uint64_t key) {
+  const uint64_t y = (ctr0 + elem_ctr<K>(i)) * key;
+  if constexpr (Kind<K>::SPLIT) {
+    uint32_t lo, hi;
+    split_pair<K>(y, y + key, lo, hi);
+    *(uint32_t*)p = (i & 1) ? hi : lo;
+  } else {
+    const uint64_t v = gen_bits<K>(y, y + key);
+    if constexpr (Kind<K>::W == 4) *(uint32_t*)p = (uint32_t)v;
+    else *(uint64_t*)p = v;
+  }
+}
+
+// The integer a reduce of kind K sums for one counter (the value is that
+// integer times 2^-24 for F32 and F32X2 and 2^-53 for F64).  Split kinds
+// sum both halves of the counter's squares64 output.
 template <int K>
 __device__ __forceinline__ uint64_t sum_term(uint64_t y, uint64_t z) {
   if constexpr (K == 0) return sq32(y, z);
   if constexpr (K == 1) return sq32(y, z) >> 8;
   if constexpr (K == 2) return sq64(y, z);
   if constexpr (K == 3) return sq64(y, z) >> 11;
+  if constexpr (K == 4) {
+    const uint64_t v = sq64(y, z);
+    return (v & 0xFFFFFFFFull) + (v >> 32);
+  }
+  if constexpr (K == 5) {
+    const uint64_t v = sq64(y, z);
+    return (((uint32_t)v) >> 8) + (v >> 40);
+  }
+}
+
+// The low-half term of a split kind (the last element of an odd count).
+template <int K>
+__device__ __forceinline__ uint64_t split_lo_term(uint64_t y, uint64_t z) {
+  const uint32_t lo = (uint32_t)sq64(y, z);
+  return K == 5 ? (lo >> 8) : lo;
 }
 
 }  // namespace sqd

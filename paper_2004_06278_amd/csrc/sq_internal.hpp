@@ -14,7 +14,17 @@ namespace sqi {
 // ---------------------------------------------------------------- errors
 int fail(int status, const std::string& msg);            // records msg, returns status
 int fail_hip(hipError_t e, const char* what);            // SQ_EHIP with the HIP message
-inline int kind_bytes(int kind) { return kind == SQ_U32 || kind == SQ_F32 ? 4 : (kind == SQ_U64 || kind == SQ_F64 ? 8 : 0); }
+// Bytes per output element (0 for an unknown kind) and the alignment an
+// output pointer or batch offset needs (split kinds write whole squares64
+// outputs, so they need 8).
+inline int kind_bytes(int kind) {
+  switch (kind) {
+    case SQ_U32: case SQ_F32: case SQ_U32X2: case SQ_F32X2: return 4;
+    case SQ_U64: case SQ_F64: return 8;
+    default: return 0;
+  }
+}
+inline int kind_align(int kind) { return kind == SQ_U32 || kind == SQ_F32 ? 4 : (kind_bytes(kind) ? 8 : 0); }
 
 // ---------------------------------------------------------------- device
 struct DeviceInfo {

@@ -29,8 +29,8 @@ struct FillArgs {
   unsigned char* out;   // address of element 0 (element-aligned)
   uint64_t nvec;        // full 16-byte vectors in the aligned body
   uint64_t nchunks;     // ceil(nvec / (block * U))
-  uint64_t y_body;      // (ctr0 + head) * key: first Weyl term of the body
-  uint64_t ekey;        // E * key: Weyl step from one vector to the next
+  uint64_t y_body;      // first Weyl term of the body: (ctr0 + counter offset of head) * key
+  uint64_t ekey;        // CPV * key: Weyl step from one vector to the next
   uint32_t head;        // elements before the 1 KiB aligned body (< 1024 / W)
   uint32_t tail;        // elements after the last full vector (0..3)
   uint32_t xcd_map;     // chunk order, see sq_launch_cfg
@@ -45,7 +45,7 @@ __device__ __forceinline__ void fill_edges(const FillArgs& a) {
   if (blockIdx.x != 0) return;
   for (uint32_t t = threadIdx.x; t < a.head + a.tail; t += blockDim.x) {
     const uint64_t i = t < a.head ? (uint64_t)t : a.head + a.nvec * E + (t - a.head);
-    store_one<K>(a.out + i * W, (a.ctr0 + i) * a.key, a.key);
+    store_elem<K>(a.out + i * W, a.ctr0, i, a.key);
   }
 }
 
@@ -106,12 +106,23 @@ FillKernel fill_kernel_for(uint32_t unroll) {
   return unroll == 4 ? k_fill<K, 4> : k_fill<K, 8>;
 }
 
+FillKernel fill_kernel(int kind, uint32_t unroll) {
+  switch (kind) {
+    case SQ_U32: return fill_kernel_for<0>(unroll);
+    case SQ_F32: return fill_kernel_for<1>(unroll);
+    case SQ_U64: return fill_kernel_for<2>(unroll);
+    case SQ_F64: return fill_kernel_for<3>(unroll);
+    case SQ_U32X2: return fill_kernel_for<4>(unroll);
+    default: return fill_kernel_for<5>(unroll);
+  }
+}
+
 // ============================================================== reduce
 struct ReduceArgs {
   uint64_t key;
   uint64_t ctr0;
-  uint64_t n;
-  uint64_t per;          // outputs per thread (contiguous counters)
+  uint64_t n;            // counters to sum (split kinds: pairs of outputs)
+  uint64_t per;          // counters per thread (contiguous)
   uint64_t* partials;    // 2 x u64 per workgroup
 };
 
@@ -192,6 +203,7 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a) {
     // flushed before it could overflow.  F32 terms are < 2^24, so 256 of them
     // fit a 32-bit partial: one 32-bit add per output instead of a 64-bit one.
     typedef typename std::conditional<K == 1, uint32_t, uint64_t>::type Part;
+    // split kinds: < 2^33 (U32X2) or < 2^25 (F32X2) per counter
     constexpr uint64_t FLUSH = K == 3 ? 1024 : (K == 1 ? 256 : (1u << 20));
     uint64_t i = 0;
     while (i < cnt) {
@@ -242,12 +254,18 @@ __device__ double round_scaled(uint64_t lo, uint64_t hi, int e) {
   return ldexp((double)mant, s + e);
 }
 
+// Sums the workgroup partials.  For a split kind with an odd count, the
+// last output (the low half of the counter after the last full pair, whose
+// first Weyl term is y_tail) is added here (split_tail: 4 or 5, else 0).
 __global__ __launch_bounds__(256) void k_reduce_final(const uint64_t* partials, uint32_t nparts, uint64_t n, int e,
+                                                      int split_tail, uint64_t y_tail, uint64_t key,
                                                       sq_sum_result* out) {
   uint64_t lo = 0, hi = 0;
   for (uint32_t i = threadIdx.x; i < nparts; i += blockDim.x) add128(lo, hi, partials[2 * i], partials[2 * i + 1]);
   block_sum128(lo, hi);
   if (threadIdx.x == 0) {
+    if (split_tail == 4) add128(lo, hi, split_lo_term<4>(y_tail, y_tail + key), 0);
+    if (split_tail == 5) add128(lo, hi, split_lo_term<5>(y_tail, y_tail + key), 0);
     out->lo = lo;
     out->hi = hi;
     out->value = round_scaled(lo, hi, e);
@@ -265,6 +283,17 @@ ReduceKernel reduce_kernel_for(uint32_t unroll) {
   }
 }
 
+ReduceKernel reduce_kernel(int kind, uint32_t unroll) {
+  switch (kind) {
+    case SQ_U32: return reduce_kernel_for<0>(unroll);
+    case SQ_F32: return reduce_kernel_for<1>(unroll);
+    case SQ_U64: return reduce_kernel_for<2>(unroll);
+    case SQ_F64: return reduce_kernel_for<3>(unroll);
+    case SQ_U32X2: return reduce_kernel_for<4>(unroll);
+    default: return reduce_kernel_for<5>(unroll);
+  }
+}
+
 // ============================================================== batch
 // Tiles of stream s under tile size 2^lg, or 0 (and *bad = 1) when the
 // descriptor is invalid: unknown kind, offset not a multiple of the element
@@ -272,8 +301,9 @@ ReduceKernel reduce_kernel_for(uint32_t unroll) {
 __device__ __forceinline__ uint64_t stream_tiles(const sqi::BatchDesc& d, uint32_t s, uint32_t lg, uint32_t* bad) {
   const uint32_t kind = d.kinds[s];
   const uint64_t len = d.lens[s], off = d.offs[s];
-  const uint32_t W = kind < 2 ? 4u : 8u;
-  if (kind > 3 || (off & (W - 1)) != 0 || off > d.out_bytes || len > (d.out_bytes - off) / W) {
+  const uint32_t W = (kind < 2 || kind > 3) ? 4u : 8u;  // element bytes
+  const uint32_t A = kind < 2 ? 4u : 8u;                // offset alignment (split kinds: whole squares64)
+  if (kind > 5 || (off & (A - 1)) != 0 || off > d.out_bytes || len > (d.out_bytes - off) / W) {
     *bad += 1;
     return 0;
   }
@@ -354,11 +384,11 @@ __device__ __forceinline__ void fill_range(uint64_t key, uint64_t ctr, uint64_t 
   const uint64_t tail = cnt - head - nvec * E;
   for (uint64_t t = tid; t < head + tail; t += B) {
     const uint64_t i = t < head ? t : head + nvec * E + (t - head);
-    store_one<K>(p + i * W, (ctr + i) * key, key);
+    store_elem<K>(p + i * W, ctr, i, key);
   }
   u32x4* body = (u32x4*)(p + head * W);
-  const uint64_t ekey = (uint64_t)E * key;
-  const uint64_t y_body = (ctr + head) * key;
+  const uint64_t ekey = (uint64_t)Kind<K>::CPV * key;
+  const uint64_t y_body = (ctr + elem_ctr<K>(head)) * key;  // head is even for split kinds
   const uint64_t step = (uint64_t)B * ekey;
   const uint64_t per_chunk = (uint64_t)B * U;
 #pragma unroll 1
@@ -398,13 +428,16 @@ __global__ __launch_bounds__(1024) void k_batch_fill(sqi::BatchDesc d, uint32_t 
     const uint64_t len = d.lens[s];
     const uint64_t cnt = len - off < T ? len - off : T;
     const uint32_t kind = d.kinds[s];
-    const uint64_t key = d.keys[s], ctr = d.ctr0s[s] + off;
-    unsigned char* p = d.out + d.offs[s] + off * (kind < 2 ? 4u : 8u);
+    const bool split = kind > 3;  // two elements per counter; tiles hold an even count
+    const uint64_t key = d.keys[s], ctr = d.ctr0s[s] + (split ? off >> 1 : off);
+    unsigned char* p = d.out + d.offs[s] + off * ((kind == 2 || kind == 3) ? 8u : 4u);
     switch (kind) {
       case 0: fill_range<0>(key, ctr, cnt, p); break;
       case 1: fill_range<1>(key, ctr, cnt, p); break;
       case 2: fill_range<2>(key, ctr, cnt, p); break;
-      default: fill_range<3>(key, ctr, cnt, p); break;
+      case 3: fill_range<3>(key, ctr, cnt, p); break;
+      case 4: fill_range<4>(key, ctr, cnt, p); break;
+      default: fill_range<5>(key, ctr, cnt, p); break;
     }
   }
 }
@@ -422,9 +455,9 @@ __global__ __launch_bounds__(256) void k_tick_expand(const sqi::TickHdr* th, con
   if (i >= m) return;
   const sqi::TickEntry e = ent[i];
   sqi::SlotDev& s = slots[e.slot];
-  const uint32_t W = s.kind < 2 ? 4u : 8u;
+  const uint32_t W = (s.kind == 2 || s.kind == 3) ? 8u : 4u;
   keys[i] = s.key;
-  ctr0s[i] = s.ctr0 + e.first;
+  ctr0s[i] = s.ctr0 + (s.kind > 3 ? e.first >> 1 : e.first);  // first is even for split kinds
   lens[i] = e.count;
   offs[i] = s.out_off + e.first * W;
   kinds[i] = (uint8_t)s.kind;
@@ -453,22 +486,16 @@ hipError_t launch_fill(int kind, uint64_t key, uint64_t ctr0, uint64_t n, void* 
   a.tail = (uint32_t)(n - head - a.nvec * E);
   const uint64_t per_chunk = (uint64_t)cfg.block * cfg.unroll;
   a.nchunks = (a.nvec + per_chunk - 1) / per_chunk;
-  a.y_body = (ctr0 + head) * key;
-  a.ekey = (uint64_t)E * key;
+  const bool split = kind == SQ_U32X2 || kind == SQ_F32X2;  // head is even: out is 8-byte aligned
+  a.y_body = (ctr0 + (split ? head / 2 : head)) * key;
+  a.ekey = (uint64_t)(split ? 2 : E) * key;
   uint64_t grid = (uint64_t)device_info().cus * cfg.grid_per_cu;
   if (grid > a.nchunks) grid = a.nchunks;
   a.xcd_map = cfg.xcd_map;
   if (a.xcd_map && grid >= 8) grid &= ~7ull;  // XCD-contiguous order needs a multiple of 8
   else a.xcd_map = 0;
   if (grid == 0) grid = 1;                      // the head/tail elements still need a workgroup
-  FillKernel k = nullptr;
-  switch (kind) {
-    case SQ_U32: k = fill_kernel_for<0>(cfg.unroll); break;
-    case SQ_F32: k = fill_kernel_for<1>(cfg.unroll); break;
-    case SQ_U64: k = fill_kernel_for<2>(cfg.unroll); break;
-    default: k = fill_kernel_for<3>(cfg.unroll); break;
-  }
-  hipLaunchKernelGGL(k, dim3((uint32_t)grid), dim3(cfg.block), 0, s, a);
+  hipLaunchKernelGGL(fill_kernel(kind, cfg.unroll), dim3((uint32_t)grid), dim3(cfg.block), 0, s, a);
   return hipGetLastError();
 }
 
@@ -488,18 +515,14 @@ static int resident_blocks(const void* k, uint32_t block) {
 hipError_t launch_reduce(int kind, uint64_t key, uint64_t ctr0, uint64_t n, sq_sum_result* out, void* ws,
                          const sq_launch_cfg& cfg, hipStream_t s) {
   const uint32_t B = 256;  // reduce workgroups are 256 threads (block_sum128 LDS sized for <= 1024)
-  ReduceKernel k = nullptr;
-  switch (kind) {
-    case SQ_U32: k = reduce_kernel_for<0>(cfg.unroll); break;
-    case SQ_F32: k = reduce_kernel_for<1>(cfg.unroll); break;
-    case SQ_U64: k = reduce_kernel_for<2>(cfg.unroll); break;
-    default: k = reduce_kernel_for<3>(cfg.unroll); break;
-  }
+  ReduceKernel k = reduce_kernel(kind, cfg.unroll);
+  const bool split = kind == SQ_U32X2 || kind == SQ_F32X2;
+  const uint64_t units = split ? n / 2 : n;  // counters with all their outputs summed
   // Every thread gets the same amount of work, so the grid must be resident
   // at once: a second partial wave of workgroups would double the time.
   const uint32_t gpc = std::min<uint32_t>(cfg.grid_per_cu, (uint32_t)resident_blocks((const void*)k, B));
   uint64_t grid = (uint64_t)device_info().cus * gpc;
-  const uint64_t need = (n + B - 1) / B;  // at least one output per thread
+  const uint64_t need = (units + B - 1) / B;  // at least one counter per thread
   if (grid > need) grid = need;
   if (grid == 0) grid = 1;
   if (grid > kReduceMaxParts) grid = kReduceMaxParts;
@@ -507,14 +530,17 @@ hipError_t launch_reduce(int kind, uint64_t key, uint64_t ctr0, uint64_t n, sq_s
   ReduceArgs a{};
   a.key = key;
   a.ctr0 = ctr0;
-  a.n = n;
-  a.per = n / T + (n % T != 0);
+  a.n = units;
+  a.per = units / T + (units % T != 0);
   a.partials = (uint64_t*)ws;
   hipLaunchKernelGGL(k, dim3((uint32_t)grid), dim3(B), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int scale = kind == SQ_F32 ? -24 : (kind == SQ_F64 ? -53 : 0);
-  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, (const uint64_t*)ws, (uint32_t)grid, n, scale, out);
+  const int scale = (kind == SQ_F32 || kind == SQ_F32X2) ? -24 : (kind == SQ_F64 ? -53 : 0);
+  const int split_tail = (split && (n & 1)) ? kind : 0;
+  const uint64_t y_tail = (ctr0 + units) * key;
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, (const uint64_t*)ws, (uint32_t)grid, n, scale,
+                     split_tail, y_tail, key, out);
   return hipGetLastError();
 }
 

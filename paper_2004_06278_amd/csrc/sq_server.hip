@@ -14,9 +14,10 @@
 //   3. if a tick stream is idle and some admitted request has outputs left,
 //      build a tick: the next chunk (at most chunk_cap outputs) of every such
 //      request, written into that stream's pinned tick buffer, which the
-//      tick's first kernel reads directly; then replay the stream's captured
-//      graph (expand -> tile scan -> persistent fill) after waiting for the
-//      control stream's latest slot upload.
+//      tick's first kernel reads directly; then (with the lock released)
+//      replay the stream's captured graph (expand -> tile scan -> tile map ->
+//      persistent fill) after waiting for the control stream's latest slot
+//      upload.
 // Up to n_streams ticks are in flight at once, so requests admitted while
 // others run share the device with them.
 #include <hip/hip_runtime.h>
@@ -109,7 +110,9 @@ struct TickLane {
   hipGraphExec_t exec = nullptr;
   unsigned char* host_buf = nullptr;  // pinned: TickHdr + entries, read by the device
   void* ws = nullptr;                 // device tick workspace
-  bool busy = false;
+  bool busy = false;                  // a tick was built for this lane and has not retired
+  bool finished = false;              // its completion event fired (scheduler thread only)
+  hipError_t status = hipSuccess;     // event status at completion
   std::vector<uint64_t> reqs;         // requests with a chunk in the running tick
 };
 
@@ -146,14 +149,14 @@ struct sq_server {
   void loop();
   bool retire_locked();
   bool admit_locked(std::vector<uint32_t>* new_slots);
-  bool tick_locked(const std::vector<uint32_t>& new_slots);
+  TickLane* build_tick_locked();
   void finish_locked(Req& r);
 };
 
 void sq_server::finish_locked(Req& r) {
   r.st = St::Done;
   r.t_done = now_s();
-  lat.push_back(r.t_done - r.t_submit);
+  if (!(r.flags & SQ_SERVE_NO_STATS)) lat.push_back(r.t_done - r.t_submit);
   ++completed;
   outputs += r.n;
   bytes_done += r.bytes;
@@ -169,14 +172,14 @@ void sq_server::finish_locked(Req& r) {
   cv_done.notify_all();
 }
 
-// Retires finished ticks; returns true if any retired.
+// Retires the lanes whose tick finished (their `finished` flag was set by
+// the scheduler outside the lock); returns true if any retired.
 bool sq_server::retire_locked() {
   bool any = false;
   for (auto& L : lanes) {
-    if (!L.busy) continue;
-    hipError_t q = hipEventQuery(L.done);
-    if (q == hipErrorNotReady) continue;
-    if (q != hipSuccess && fatal.empty()) fatal = std::string("tick: ") + hipGetErrorString(q);
+    if (!L.finished) continue;
+    if (L.status != hipSuccess && fatal.empty()) fatal = std::string("tick: ") + hipGetErrorString(L.status);
+    L.finished = false;
     L.busy = false;
     any = true;
     for (uint64_t id : L.reqs) {
@@ -216,20 +219,15 @@ bool sq_server::admit_locked(std::vector<uint32_t>* new_slots) {
   return any;
 }
 
-// Builds and launches one tick on an idle lane; returns true if launched.
-bool sq_server::tick_locked(const std::vector<uint32_t>& new_slots) {
-  if (!new_slots.empty()) {
-    for (uint32_t s : new_slots) {
-      hipError_t e = hipMemcpyAsync(slots_dev + s, slots_stage + s, sizeof(SlotDev), hipMemcpyHostToDevice, ctl);
-      if (e != hipSuccess) { if (fatal.empty()) fatal = std::string("slot upload: ") + hipGetErrorString(e); return false; }
-    }
-    hipError_t e = hipEventRecord(ctl_ev, ctl);
-    if (e != hipSuccess) { if (fatal.empty()) fatal = std::string("slot upload event: ") + hipGetErrorString(e); return false; }
-  }
+// Fills an idle lane's pinned tick buffer with the next chunk of every
+// admitted request that has outputs left; returns the lane, or nullptr if
+// no lane is idle or nothing is left to schedule.  The launch itself happens
+// outside the lock.
+TickLane* sq_server::build_tick_locked() {
   TickLane* L = nullptr;
   for (auto& l : lanes)
     if (!l.busy) { L = &l; break; }
-  if (L == nullptr) return false;
+  if (L == nullptr) return nullptr;
   TickHdr* th_ = (TickHdr*)L->host_buf;
   TickEntry* ent = (TickEntry*)(L->host_buf + sizeof(TickHdr));
   uint32_t m = 0;
@@ -246,42 +244,62 @@ bool sq_server::tick_locked(const std::vector<uint32_t>& new_slots) {
     L->reqs.push_back(id);
     if (++m == cfg.max_slots) break;
   }
-  if (m == 0) return false;
+  if (m == 0) return nullptr;
   th_->entries = m;
-  std::atomic_thread_fence(std::memory_order_seq_cst);  // entries visible before the launch doorbell
-  hipError_t e = hipStreamWaitEvent(L->stream, ctl_ev, 0);
-  if (e == hipSuccess) e = hipGraphLaunch(L->exec, L->stream);
-  if (e == hipSuccess) e = hipEventRecord(L->done, L->stream);
-  if (e != hipSuccess && fatal.empty()) fatal = std::string("tick launch: ") + hipGetErrorString(e);
   L->busy = true;
   ++ticks;
-  return true;
+  return L;
 }
 
+// The scheduler.  Lane state (busy, finished, event status) belongs to this
+// thread; request, queue, slot and arena state is shared and changed only
+// under `mu`.  HIP calls (event queries, slot uploads, graph launches) run
+// with the lock released, so submit()/poll() never wait behind them.
 void sq_server::loop() {
   (void)hipSetDevice(device);
-  std::unique_lock<std::mutex> lk(mu);
+  std::vector<uint32_t> new_slots;
+  std::vector<TickLane*> to_launch;
   for (;;) {
-    bool progress = retire_locked();
-    std::vector<uint32_t> new_slots;
-    progress |= admit_locked(&new_slots);
-    bool launched = false;
-    do {
-      launched = tick_locked(new_slots);
-      new_slots.clear();
-      progress |= launched;
-    } while (launched);
-    const bool inflight = std::any_of(lanes.begin(), lanes.end(), [](const TickLane& l) { return l.busy; });
-    if (stop && !inflight && active.empty() && queue.empty()) break;
-    if (!inflight && !progress) {
-      // idle: sleep until a submit (or stop) arrives
-      cv_work.wait_for(lk, std::chrono::milliseconds(20));
-    } else if (!progress) {
-      // ticks running: poll their events without holding the lock
-      lk.unlock();
-      std::this_thread::yield();
-      lk.lock();
+    for (auto& L : lanes) {
+      if (!L.busy || L.finished) continue;
+      const hipError_t q = hipEventQuery(L.done);
+      if (q == hipErrorNotReady) continue;
+      L.status = q;
+      L.finished = true;
     }
+    bool progress = false, inflight = false, exit_now = false;
+    new_slots.clear();
+    to_launch.clear();
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      progress |= retire_locked();
+      progress |= admit_locked(&new_slots);
+      while (TickLane* L = build_tick_locked()) to_launch.push_back(L);
+      inflight = std::any_of(lanes.begin(), lanes.end(), [](const TickLane& l) { return l.busy; });
+      if (stop && !inflight && active.empty() && queue.empty()) exit_now = true;
+      else if (!inflight && !progress && new_slots.empty()) cv_work.wait_for(lk, std::chrono::milliseconds(20));
+    }
+    if (exit_now) break;
+    hipError_t e = hipSuccess;
+    for (uint32_t slot : new_slots)
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(slots_dev + slot, slots_stage + slot, sizeof(SlotDev), hipMemcpyHostToDevice, ctl);
+    if (!new_slots.empty() && e == hipSuccess) e = hipEventRecord(ctl_ev, ctl);
+    std::atomic_thread_fence(std::memory_order_seq_cst);  // tick entries visible before the launch doorbell
+    for (TickLane* L : to_launch) {
+      if (e == hipSuccess) e = hipStreamWaitEvent(L->stream, ctl_ev, 0);
+      if (e == hipSuccess) e = hipGraphLaunch(L->exec, L->stream);
+      if (e == hipSuccess) e = hipEventRecord(L->done, L->stream);
+      if (e != hipSuccess) {  // the lane never runs: retire it at once with the error
+        L->status = e;
+        L->finished = true;
+      }
+    }
+    if (e != hipSuccess) {
+      std::lock_guard<std::mutex> g(mu);
+      if (fatal.empty()) fatal = std::string("server launch: ") + hipGetErrorString(e);
+    }
+    if (!progress && to_launch.empty() && inflight) std::this_thread::yield();  // ticks running: poll again
   }
 }
 
@@ -315,6 +333,7 @@ int sq_server_create(const sq_server_cfg* cfg, sq_server** out) {
   if (rc != SQ_OK) return rc;
   sq_server* s = new sq_server();
   s->cfg = *cfg;
+  s->cfg.chunk_cap &= ~1ull;  // chunks of split kinds must start at a low word
   s->device = device_info().device;
   s->lcfg = tuned_cfg(SQ_OP_BATCH, SQ_U32, cfg->chunk_cap);
   if (cfg->tile_log2) s->lcfg.tile_log2 = cfg->tile_log2;

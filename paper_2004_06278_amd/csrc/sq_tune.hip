@@ -21,7 +21,7 @@
 
 namespace sqi {
 
-static constexpr int kOps = 3, kKinds = 4, kBuckets = 5;
+static constexpr int kOps = 3, kKinds = 6, kBuckets = 5;
 
 struct Entry {
   sq_launch_cfg cfg;
@@ -67,7 +67,7 @@ sq_launch_cfg default_cfg(sq_op op, int kind, uint64_t n) {
 
 sq_launch_cfg tuned_cfg(sq_op op, int kind, uint64_t n) {
   std::lock_guard<std::mutex> g(g_tab_mu);
-  const Entry& e = g_tab[op][kind & 3][bucket_of(n)];
+  const Entry& e = g_tab[op][(kind >= 0 && kind < kKinds) ? kind : 0][bucket_of(n)];
   return e.set ? e.cfg : default_cfg(op, kind, n);
 }
 

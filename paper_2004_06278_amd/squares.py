@@ -17,10 +17,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsquares.so")
 TUNE_TABLE = os.path.join(HERE, "tune_gfx950.json")
 
-U32, F32, U64, F64 = 0, 1, 2, 3
-KIND_BYTES = {U32: 4, F32: 4, U64: 8, F64: 8}
+U32, F32, U64, F64, U32X2, F32X2 = 0, 1, 2, 3, 4, 5
+KIND_BYTES = {U32: 4, F32: 4, U64: 8, F64: 8, U32X2: 4, F32X2: 4}
 OP_FILL, OP_REDUCE, OP_BATCH = 0, 1, 2
 SERVE_DISCARD = 1
+SERVE_NO_STATS = 2
 
 STATUS = {0: "SQ_OK", -1: "SQ_EINVAL", -2: "SQ_EALIGN", -3: "SQ_ENOMEM", -4: "SQ_EHIP", -5: "SQ_EBUSY",
           -6: "SQ_ENOTFOUND"}
@@ -72,6 +73,8 @@ SIGNATURES = {
     "sq64_fill": (_int, [_u64, _u64, _u64, _vp, _vp]),
     "sq_uniform_f32": (_int, [_u64, _u64, _u64, _vp, _vp]),
     "sq_uniform_f64": (_int, [_u64, _u64, _u64, _vp, _vp]),
+    "sq64x2_fill": (_int, [_u64, _u64, _u64, _vp, _vp]),
+    "sq_uniform_f32x2": (_int, [_u64, _u64, _u64, _vp, _vp]),
     "sq_fill": (_int, [_int, _u64, _u64, _u64, _vp, _vp]),
     "sq_fill_cfg": (_int, [_int, _u64, _u64, _u64, _vp, ctypes.POINTER(LaunchCfg), _vp]),
     "sq_tune_get": (_int, [_int, _int, _u64, ctypes.POINTER(LaunchCfg)]),
@@ -161,7 +164,8 @@ _DTYPES = None
 
 def kind_dtype(kind: int):
     torch = _torch()
-    return {U32: torch.uint32, F32: torch.float32, U64: torch.uint64, F64: torch.float64}[kind]
+    return {U32: torch.uint32, F32: torch.float32, U64: torch.uint64, F64: torch.float64, U32X2: torch.uint32,
+            F32X2: torch.float32}[kind]
 
 
 def cfg(block=1024, unroll=8, grid_per_cu=16, xcd_map=0, tile_log2=16) -> LaunchCfg:
@@ -207,6 +211,20 @@ def uniform_f32(key, ctr0, n, out=None, stream=None):
     torch = _torch()
     out = torch.empty(n, dtype=torch.float32, device="cuda") if out is None else out
     check(lib().sq_uniform_f32(key & (2**64 - 1), ctr0 & (2**64 - 1), n, _ptr(out), _stream(stream)))
+    return out
+
+
+def sq64x2_fill(key, ctr0, n, out=None, stream=None):
+    torch = _torch()
+    out = torch.empty(n, dtype=torch.uint32, device="cuda") if out is None else out
+    check(lib().sq64x2_fill(key & (2**64 - 1), ctr0 & (2**64 - 1), n, _ptr(out), _stream(stream)))
+    return out
+
+
+def uniform_f32x2(key, ctr0, n, out=None, stream=None):
+    torch = _torch()
+    out = torch.empty(n, dtype=torch.float32, device="cuda") if out is None else out
+    check(lib().sq_uniform_f32x2(key & (2**64 - 1), ctr0 & (2**64 - 1), n, _ptr(out), _stream(stream)))
     return out
 
 

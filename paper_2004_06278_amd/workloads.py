@@ -16,10 +16,12 @@ from dataclasses import dataclass
 
 import numpy as np
 
-# Output kinds: U32/F32 come from squares32, U64/F64 from squares64.
-U32, F32, U64, F64 = 0, 1, 2, 3
-KIND_BYTES = {U32: 4, F32: 4, U64: 8, F64: 8}
-KIND_NAMES = {U32: "u32", F32: "f32", U64: "u64", F64: "f64"}
+# Output kinds: U32/F32 come from squares32, U64/F64 from squares64, and
+# U32X2/F32X2 split each squares64 output into two 32-bit outputs.
+U32, F32, U64, F64, U32X2, F32X2 = 0, 1, 2, 3, 4, 5
+KIND_BYTES = {U32: 4, F32: 4, U64: 8, F64: 8, U32X2: 4, F32X2: 4}
+KIND_ALIGN = {U32: 4, F32: 4, U64: 8, F64: 8, U32X2: 8, F32X2: 8}
+KIND_NAMES = {U32: "u32", F32: "f32", U64: "u64", F64: "f64", U32X2: "u32x2", F32X2: "f32x2"}
 
 MASK64 = (1 << 64) - 1
 
@@ -107,7 +109,7 @@ def pack_offsets(lens: np.ndarray, kinds: np.ndarray, g: np.random.Generator | N
     offs = np.zeros(len(sizes), dtype=np.uint64)
     pos = 0
     for s, sz in enumerate(sizes):
-        a = KIND_BYTES[int(kinds[s])] if align < KIND_BYTES[int(kinds[s])] else align
+        a = max(KIND_ALIGN[int(kinds[s])], align)
         if g is not None and max_pad_words > 0:
             pos += a * int(g.integers(0, max_pad_words + 1))
         pos = (pos + a - 1) // a * a

@@ -7,8 +7,18 @@ import threading
 
 import numpy as np
 
-KIND_BYTES = {0: 4, 1: 4, 2: 8, 3: 8}
-NP_DTYPE = {0: np.uint32, 1: np.float32, 2: np.uint64, 3: np.float64}
+KIND_BYTES = {0: 4, 1: 4, 2: 8, 3: 8, 4: 4, 5: 4}
+KIND_ALIGN = {0: 4, 1: 4, 2: 8, 3: 8, 4: 8, 5: 8}
+NP_DTYPE = {0: np.uint32, 1: np.float32, 2: np.uint64, 3: np.float64, 4: np.uint32, 5: np.float32}
+
+
+def oracle_element(o, kind: int, key: int, ctr0: int, i: int) -> bytes:
+    """Bytes of element i of a fill of `kind` from counter ctr0 (split kinds
+    take word i & 1 of squares64 at ctr0 + i // 2)."""
+    if kind in (4, 5):
+        pair = o.fill(kind, key, (ctr0 + i // 2) % 2**64, 2).view(np.uint8)
+        return pair[4 * (i & 1): 4 * (i & 1) + 4].tobytes()
+    return o.fill(kind, key, (ctr0 + i) % 2**64, 1).view(np.uint8).tobytes()
 HOST_THREADS = max(1, min(16, os.cpu_count() or 1))
 
 

@@ -28,7 +28,7 @@ def test_batch_small_random(sq, oracle_mod, seed):
     zero and even keys; several tile sizes so streams span many tiles."""
     from paper_2004_06278_amd import workloads as W
 
-    b = W.small_random_batch(seed=seed, m=300, max_len=20000)
+    b = W.small_random_batch(seed=seed, m=300, max_len=20000, kinds=(0, 1, 2, 3, 4, 5))
     ref = _oracle_arena(oracle_mod, b)
     db = sq.batch_to_device(b.keys, b.ctr0s, b.lens, b.offs, b.kinds, b.arena_bytes)
     for tl in (12, 13, 16, 24):
@@ -50,7 +50,7 @@ def test_batch_equals_per_stream_fills(sq):
 
     from paper_2004_06278_amd import workloads as W
 
-    b = W.small_random_batch(seed=9, m=150, max_len=50000)
+    b = W.small_random_batch(seed=9, m=150, max_len=50000, kinds=(0, 1, 2, 3, 4, 5))
     db = sq.batch_to_device(b.keys, b.ctr0s, b.lens, b.offs, b.kinds, b.arena_bytes)
     sq.fill_batch(db)
     arena = to_host_bytes(db.out)

@@ -5,11 +5,11 @@ from __future__ import annotations
 import numpy as np
 import pytest
 
-from gpu_helpers import HOST_THREADS, KIND_BYTES, first_diff, log, oracle_bytes, to_host_bytes
+from gpu_helpers import HOST_THREADS, KIND_ALIGN, KIND_BYTES, first_diff, log, oracle_bytes, oracle_element, to_host_bytes
 
 pytestmark = pytest.mark.gpu
 
-KINDS = [0, 1, 2, 3]
+KINDS = [0, 1, 2, 3, 4, 5]  # U32, F32, U64, F64, U32X2, F32X2
 
 
 @pytest.fixture(scope="module")
@@ -31,13 +31,13 @@ def test_fill_small_random_misaligned(sq, oracle_mod, kind):
     import torch
 
     g = np.random.Generator(np.random.PCG64(100 + kind))
-    W = KIND_BYTES[kind]
+    W, A = KIND_BYTES[kind], KIND_ALIGN[kind]
     buf = torch.empty(5000 * 8 + 2048, dtype=torch.uint8, device="cuda")
     for trial in range(60):
         n = int(g.integers(0, 5001)) if trial > 3 else [0, 1, 2, 3][trial]
         # start offsets across a whole KiB: the kernel writes a head of up to
         # 1024/W elements one by one before its first aligned KiB
-        off = W * int(g.integers(0, 1024 // W + 2))
+        off = A * int(g.integers(0, 1024 // A + 2))
         key = int(g.integers(0, 2**64, dtype=np.uint64))
         ctr0 = int(g.integers(0, 2**64, dtype=np.uint64)) if trial % 3 else 2**64 - int(g.integers(1, 3000))
         log(f"fill kind={kind} trial={trial} n={n} off={off} key={key:#x} ctr0={ctr0:#x}")
@@ -80,6 +80,9 @@ def test_invalid_arguments(sq):
         sq.fill_ptr(2, 1, 0, 2, buf.data_ptr() + 4)  # not 8-byte aligned for u64
     assert e.value.status == -2
     with pytest.raises(sq.SquaresError) as e:
+        sq.fill_ptr(4, 1, 0, 2, buf.data_ptr() + 4)  # split kinds write whole squares64 outputs
+    assert e.value.status == -2
+    with pytest.raises(sq.SquaresError) as e:
         sq.fill_ptr(7, 1, 0, 2, buf.data_ptr())  # unknown kind
     assert e.value.status == -1
     with pytest.raises(sq.SquaresError) as e:
@@ -105,14 +108,16 @@ def test_argument_order_matches_paper_scalar(sq, oracle_mod):
 
 def test_named_entry_points(sq, oracle_mod):
     key, ctr0, n = 0x7A3C91E4B85D2F60, 12345, 10007
-    for fn, kind in ((sq.sq32_fill, 0), (sq.uniform_f32, 1), (sq.sq64_fill, 2), (sq.uniform_f64, 3)):
+    for fn, kind in ((sq.sq32_fill, 0), (sq.uniform_f32, 1), (sq.sq64_fill, 2), (sq.uniform_f64, 3),
+                     (sq.sq64x2_fill, 4), (sq.uniform_f32x2, 5)):
         out = fn(key, ctr0, n)
         assert to_host_bytes(out).tobytes() == oracle_bytes(oracle_mod, kind, key, ctr0, n).tobytes()
 
 
 def test_plain_fill_64mib(sq, oracle_mod):
     """The 64 MiB squares32 fill (one distinct-digit key, counters 0..2^24-1)
-    in full, plus squares64 on the same counters and the hi32 identity."""
+    in full, plus squares64 on the same counters, the hi32 identity, and the
+    split kind (the squares64 words, high words equal to squares32)."""
     from paper_2004_06278_amd import workloads as W
 
     c = W.plain_fill_case()
@@ -123,6 +128,9 @@ def test_plain_fill_64mib(sq, oracle_mod):
     u64 = sq.sq64_fill(c.key, c.ctr0, c.n).cpu().numpy()
     assert np.array_equal(u64 >> np.uint64(32), u32.astype(np.uint64))
     assert np.array_equal(u64, oracle_mod.fill(2, c.key, c.ctr0, c.n, threads=HOST_THREADS))
+    x2 = sq.sq64x2_fill(c.key, c.ctr0, 2 * c.n).cpu().numpy()
+    assert x2.tobytes() == u64.tobytes()
+    assert np.array_equal(x2[1::2], u32)
 
 
 @pytest.mark.parametrize("kind", KINDS)
@@ -145,7 +153,6 @@ def test_full_size_sampled(sq, oracle_mod, kind):
                                     g.integers(0, n, size=1 << 16)]))
     got = iv[torch.from_numpy(idx.astype(np.int64)).cuda()].cpu().numpy().view(np.uint8).reshape(-1, W_)
     for row, i in zip(got, idx):
-        ref = oracle_mod.fill(kind, c.key, (c.ctr0 + int(i)) % 2**64, 1).view(np.uint8)
-        assert row.tobytes() == ref.tobytes(), f"position {int(i)}"
+        assert row.tobytes() == oracle_element(oracle_mod, kind, c.key, c.ctr0, int(i)), f"position {int(i)}"
     del out, iv
     torch.cuda.empty_cache()

@@ -9,7 +9,7 @@ from gpu_helpers import HOST_THREADS, log
 
 pytestmark = pytest.mark.gpu
 
-KINDS = [0, 1, 2, 3]
+KINDS = [0, 1, 2, 3, 4, 5]
 
 
 @pytest.fixture(scope="module")
@@ -53,13 +53,14 @@ def test_reduce_additive(sq, kind):
     """reduce[a, b) + reduce[b, c) == reduce[a, c), across the counter wrap."""
     key, a = 0x0F1E2D3C4B5A6978, 2**64 - 3_000_000
     whole, _, _ = sq.reduce(kind, key, a, 10_000_000)
-    for b in (1, 2_999_999, 3_000_000, 7_777_777):
+    per_ctr = 2 if kind in (4, 5) else 1  # split kinds: a part starting at an even output starts a counter
+    for b in (2, 2_999_998, 3_000_000, 7_777_778):
         l, _, _ = sq.reduce(kind, key, a, b)
-        r, _, _ = sq.reduce(kind, key, (a + b) % 2**64, 10_000_000 - b)
+        r, _, _ = sq.reduce(kind, key, (a + b // per_ctr) % 2**64, 10_000_000 - b)
         assert l + r == whole
 
 
-@pytest.mark.parametrize("kind", [1, 3])
+@pytest.mark.parametrize("kind", [1, 3, 5])
 def test_reduce_full_size_exact(sq, oracle_mod, kind):
     """The fused F32 / F64 consumers over n = 2^32 outputs from a random
     counter (the single-key workload), compared with the oracle's exact sum

@@ -45,6 +45,8 @@ def test_server_alone_equals_mix_equals_oracle(sq, oracle_mod, n_streams, chunk_
     assert alone.tobytes() == ref.tobytes(), first_diff(alone, ref)
 
     reqs = _mix(seed=40 + n_streams, r=120, max_log2=17)
+    # split-word requests too (odd lengths end on a low word)
+    reqs += [(4 + (i % 2), 0x3F1E5D7C9B2A4068 + i, 2**64 - 1000 * i - 1, 1000 * i + 7) for i in range(1, 9)]
     reqs.insert(60, probe)
     log(f"server mix of {len(reqs)} requests")
     with sq.Server(256 << 20, max_slots=48, chunk_cap=chunk_cap, n_streams=n_streams) as srv:
