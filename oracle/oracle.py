@@ -75,6 +75,10 @@ def lib() -> ctypes.CDLL:
             L.oracle_fill_batch.restype = ctypes.c_int
             L.oracle_sum.argtypes = [ctypes.c_int, u64, u64, u64, vp]
             L.oracle_sum.restype = ctypes.c_int
+            L.oracle_fill_strided.argtypes = [ctypes.c_int, u64, u64, u64, u64, vp]
+            L.oracle_fill_strided.restype = ctypes.c_int
+            L.oracle_fill_keys.argtypes = [ctypes.c_int, u64, vp, u64, vp]
+            L.oracle_fill_keys.restype = ctypes.c_int
             _lib = L
     return _lib
 
@@ -140,6 +144,25 @@ def fill_into(kind: int, key: int, ctr0: int, out: np.ndarray, threads: int = 1)
         th.start()
     for th in ts:
         th.join()
+
+
+def fill_strided(kind: int, key: int, ctr0: int, step: int, n: int) -> np.ndarray:
+    """out[i] = kind's value at counter ctr0 + i*step (split kinds: word i%2 at
+    ctr0 + (i//2)*step)."""
+    out = np.empty(n, dtype=KIND_DTYPE[kind])
+    if lib().oracle_fill_strided(kind, key & (2**64 - 1), ctr0 & (2**64 - 1), step & (2**64 - 1), n,
+                                 _ptr(out)) != 0:
+        raise ValueError("unknown kind")
+    return out
+
+
+def fill_keys(kind: int, ctr: int, keys) -> np.ndarray:
+    """Key-counter mode: out[j] = kind's value at counter ctr under keys[j]."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    out = np.empty(keys.size, dtype=KIND_DTYPE[kind])
+    if lib().oracle_fill_keys(kind, ctr & (2**64 - 1), _ptr(keys), keys.size, _ptr(out)) != 0:
+        raise ValueError("kind not available in key-counter mode")
+    return out
 
 
 def fill_batch(keys, ctr0s, lens, offs, kinds, out_bytes: int) -> np.ndarray:

@@ -210,6 +210,52 @@ static int fill_kind(int kind, uint64_t key, uint64_t ctr0, uint64_t n,
     return 0;
 }
 
+/* Counter increments other than one (Section 4 tests them): element i uses
+ * counter ctr0 + i*step, modulo 2^64; for the split kinds element i is word
+ * i%2 of squares64 at counter ctr0 + (i/2)*step.  The second addend of each
+ * round stays (ctr+1)*key: the step changes which counters are visited, not
+ * the generator. */
+int oracle_fill_strided(int kind, uint64_t key, uint64_t ctr0, uint64_t step, uint64_t n,
+                        unsigned char *out)
+{
+    for (uint64_t i = 0; i < n; ++i) {
+        const int split = (kind == ORACLE_U32X2 || kind == ORACLE_F32X2);
+        const uint64_t c = ctr0 + (split ? i / 2 : i) * step;
+        switch (kind) {
+        case ORACLE_U32: { uint32_t v = oracle_squares32(c, key); memcpy(out + 4 * i, &v, 4); break; }
+        case ORACLE_F32: { float v = oracle_to_f32(oracle_squares32(c, key)); memcpy(out + 4 * i, &v, 4); break; }
+        case ORACLE_U64: { uint64_t v = oracle_squares64(c, key); memcpy(out + 8 * i, &v, 8); break; }
+        case ORACLE_F64: { double v = oracle_to_f64(oracle_squares64(c, key)); memcpy(out + 8 * i, &v, 8); break; }
+        case ORACLE_U32X2: case ORACLE_F32X2: {
+            const uint64_t w = oracle_squares64(c, key);
+            uint32_t h = (i % 2 == 0) ? (uint32_t)w : (uint32_t)(w >> 32);
+            if (kind == ORACLE_F32X2) { float f = oracle_to_f32(h); memcpy(out + 4 * i, &f, 4); }
+            else memcpy(out + 4 * i, &h, 4);
+            break;
+        }
+        default: return -1;
+        }
+    }
+    return 0;
+}
+
+/* Key-counter mode (Section 4): the counter is fixed and the key varies;
+ * output j is kind's value at counter ctr under keys[j] (kinds U32, F32,
+ * U64, F64). */
+int oracle_fill_keys(int kind, uint64_t ctr, const uint64_t *keys, uint64_t m, unsigned char *out)
+{
+    for (uint64_t j = 0; j < m; ++j) {
+        switch (kind) {
+        case ORACLE_U32: { uint32_t v = oracle_squares32(ctr, keys[j]); memcpy(out + 4 * j, &v, 4); break; }
+        case ORACLE_F32: { float v = oracle_to_f32(oracle_squares32(ctr, keys[j])); memcpy(out + 4 * j, &v, 4); break; }
+        case ORACLE_U64: { uint64_t v = oracle_squares64(ctr, keys[j]); memcpy(out + 8 * j, &v, 8); break; }
+        case ORACLE_F64: { double v = oracle_to_f64(oracle_squares64(ctr, keys[j])); memcpy(out + 8 * j, &v, 8); break; }
+        default: return -1;
+        }
+    }
+    return 0;
+}
+
 /* Ragged batch: stream s fills lens[s] outputs of kinds[s] from counter
  * ctr0s[s] under keys[s], written at byte offset offs[s] of `out`.  This is
  * the paper's "more keys give more streams" (Section 3) laid out as one

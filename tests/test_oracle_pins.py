@@ -391,3 +391,58 @@ def test_split_sums_and_wrap(oracle_mod, kind):
     whole = o.fill(kind, key, ctr0, n)
     parts = np.concatenate([o.fill(kind, key, ctr0, 2000), o.fill(kind, key, 0, n - 2000)])
     assert whole.tobytes() == parts.tobytes()
+
+
+# ---------------------------------------------------------------- counter increments other than one
+@pytest.mark.parametrize("kind", [0, 1, 2, 3, 4, 5])
+def test_strided_is_a_subsample_of_the_unit_fill(oracle_mod, kind):
+    """Visiting counters ctr0, ctr0+s, ctr0+2s, ... gives the outputs a unit-step
+    fill has at those counters (the step selects counters; Section 4 tests such
+    increments)."""
+    o = oracle_mod
+    key, ctr0 = 0xB4C3D2E1F0A19283, 2**64 - 500
+    split = kind in (4, 5)
+    for step in (1, 2, 3, 7, 64):
+        n = 600
+        a = o.fill_strided(kind, key, ctr0, step, n)
+        calls = (n + 1) // 2 if split else n
+        unit = o.fill(kind, key, ctr0, (2 if split else 1) * calls * step)
+        if split:
+            ref = unit.reshape(-1, 2)[::step].reshape(-1)[:n]
+        else:
+            ref = unit[::step][:n]
+        assert a.tobytes() == ref.tobytes()
+
+
+def test_strided_special_steps(oracle_mod):
+    o = oracle_mod
+    key, c = 0x1A2B3C4D5E6F7081, 12345
+    z = o.fill_strided(0, key, c, 0, 50)          # step 0: the same counter every time
+    assert np.all(z == o.squares32(c, key))
+    m = o.fill_strided(2, key, c, 2**64 - 1, 50)  # step -1 mod 2^64: counters run backwards
+    assert [int(v) for v in m] == [o.squares64((c - i) % 2**64, key) for i in range(50)]
+    big = o.fill_strided(0, key, 2**64 - 3, 2**63 + 1, 6)  # wraps on every step
+    assert [int(v) for v in big] == [o.squares32((2**64 - 3 + i * (2**63 + 1)) % 2**64, key) for i in range(6)]
+
+
+# ---------------------------------------------------------------- key-counter mode
+@pytest.mark.parametrize("kind", [0, 1, 2, 3])
+def test_key_counter_mode(oracle_mod, kind):
+    """Counter fixed, key varying (Section 4's key-counter test mode): output j
+    is the fill of keys[j] at that counter; key 0 gives 0 (closed form) and the
+    hand-worked sparse keys give their worked values."""
+    from pins import load_worked_examples
+
+    o = oracle_mod
+    g = np.random.Generator(np.random.PCG64(31))
+    keys = g.integers(0, 2**64, size=300, dtype=np.uint64)
+    keys[::17] = 0
+    for ctr in (0, 1, 2**64 - 1, 0x0123456789ABCDEF):
+        out = o.fill_keys(kind, ctr, keys)
+        for j in range(0, 300, 7):
+            assert out[j: j + 1].tobytes() == o.fill(kind, int(keys[j]), ctr, 1).tobytes()
+        if kind in (0, 2):
+            assert np.all(out[::17] == 0)
+    rows = load_worked_examples()
+    out32 = o.fill_keys(0, 1, np.array([r[1] for r in rows if r[0] == 1], dtype=np.uint64))
+    assert [int(v) for v in out32] == [r[2] for r in rows if r[0] == 1]
