@@ -79,6 +79,12 @@ def lib() -> ctypes.CDLL:
             L.oracle_fill_strided.restype = ctypes.c_int
             L.oracle_fill_keys.argtypes = [ctypes.c_int, u64, vp, u64, vp]
             L.oracle_fill_keys.restype = ctypes.c_int
+            L.oracle_key_index.argtypes = [u64]
+            L.oracle_key_index.restype = u64
+            L.oracle_key_half.argtypes = [u64]
+            L.oracle_key_half.restype = ctypes.c_uint32
+            L.oracle_make_keys.argtypes = [u64, u64, u64, vp]
+            L.oracle_make_keys.restype = ctypes.c_int
             _lib = L
     return _lib
 
@@ -162,6 +168,25 @@ def fill_keys(kind: int, ctr: int, keys) -> np.ndarray:
     out = np.empty(keys.size, dtype=KIND_DTYPE[kind])
     if lib().oracle_fill_keys(kind, ctr & (2**64 - 1), _ptr(keys), keys.size, _ptr(out)) != 0:
         raise ValueError("kind not available in key-counter mode")
+    return out
+
+
+KEY_CHOICES = 16 * 15 * 14 * 13 * 12 * 11 * 10 * 9
+
+
+def key_index(r: int) -> int:
+    return int(lib().oracle_key_index(r & (2**64 - 1)))
+
+
+def key_half(u: int) -> int:
+    return int(lib().oracle_key_half(u))
+
+
+def make_keys(gen_key: int, ctr0: int, m: int) -> np.ndarray:
+    """Distinct-digit keys: key j from squares64 at counters ctr0 + 2j and
+    ctr0 + 2j + 1 under gen_key."""
+    out = np.empty(m, dtype=np.uint64)
+    lib().oracle_make_keys(gen_key & (2**64 - 1), ctr0 & (2**64 - 1), m, _ptr(out))
     return out
 
 

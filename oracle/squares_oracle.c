@@ -256,6 +256,57 @@ int oracle_fill_keys(int kind, uint64_t ctr, const uint64_t *keys, uint64_t m, u
     return 0;
 }
 
+/* ------------------------------------------------------------------------
+ * Distinct-digit keys (Section 3, Discussion): the upper 8 hex digits of a key
+ * are mutually different, so are the lower 8, and the digits are random.
+ * The paper gives the property, not a procedure; the procedure used here is
+ * this library's own, with squares64 as the random source so that key j is a
+ * function of (gen_key, ctr0, j) alone:
+ *   half h of key j (h = 0 upper, 1 lower) draws r = squares64(ctr0 + 2j + h,
+ *   gen_key), maps it to u = floor(r * N / 2^64) with N = 16*15*...*9 (the
+ *   number of ordered choices of 8 digits out of 16), and decodes u as the
+ *   choices of a Fisher-Yates shuffle of the digits 0..15 stopped after 8
+ *   steps: step i (radix 16 - i) takes the digit at position i + (u mod
+ *   radix) of the partly shuffled list and u becomes u div radix.  The first
+ *   digit taken is the half's most significant hex digit.
+ * ------------------------------------------------------------------------ */
+#define ORACLE_KEY_CHOICES 518918400ull /* 16*15*14*13*12*11*10*9 */
+
+/* floor(r * N / 2^64), with the 128-bit product formed exactly. */
+uint64_t oracle_key_index(uint64_t r)
+{
+    unsigned __int128 p = (unsigned __int128)r * ORACLE_KEY_CHOICES;
+    return (uint64_t)(p >> 64);
+}
+
+/* The 8 hex digits (as a 32-bit half key) that index u < N selects. */
+uint32_t oracle_key_half(uint64_t u)
+{
+    int digits[16];
+    for (int i = 0; i < 16; ++i) digits[i] = i;
+    uint32_t half = 0;
+    for (int i = 0; i < 8; ++i) {
+        int radix = 16 - i;
+        int pick = i + (int)(u % (uint64_t)radix);
+        u /= (uint64_t)radix;
+        int d = digits[pick];
+        digits[pick] = digits[i];
+        digits[i] = d;
+        half = (half << 4) | (uint32_t)d;
+    }
+    return half;
+}
+
+int oracle_make_keys(uint64_t gen_key, uint64_t ctr0, uint64_t m, uint64_t *keys)
+{
+    for (uint64_t j = 0; j < m; ++j) {
+        uint64_t upper = oracle_key_half(oracle_key_index(oracle_squares64(ctr0 + 2 * j, gen_key)));
+        uint64_t lower = oracle_key_half(oracle_key_index(oracle_squares64(ctr0 + 2 * j + 1, gen_key)));
+        keys[j] = (upper << 32) | lower;
+    }
+    return 0;
+}
+
 /* Ragged batch: stream s fills lens[s] outputs of kinds[s] from counter
  * ctr0s[s] under keys[s], written at byte offset offs[s] of `out`.  This is
  * the paper's "more keys give more streams" (Section 3) laid out as one
