@@ -12,11 +12,13 @@ steps with a device synchronisation on both sides; inputs are scalars, so
 nothing is transferred.  The JSON line carries the whole-step rate, each
 kernel's average duration from HIP events on the launch stream, the
 roofline of the dominant kernel, the CPU oracle's rate on a bounded sample,
-and (unless --no-extras) the split-word variant of squares64, the
+and (unless --no-extras) the split-word variant of squares64, the counter
+modes (increments other than one, key-counter mode, key generation), the
 ragged-batch speedup over per-stream launches and serving latency
 percentiles.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--log2n 32] [--no-extras]
+                       [--extras split,modes,batch,serving] [--no-cpu]
 """
 from __future__ import annotations
 
@@ -48,9 +50,10 @@ SLOTS = {
     "sum_f64": 1.0 + 1.0,                  # 64-bit >> 11, 64-bit accumulate
 }
 KERNEL_SOURCES = ["paper_2004_06278_amd/csrc/sq_device.hpp", "paper_2004_06278_amd/csrc/sq_kernels.hip"]
-# rocprofv3 kernel-name prefixes of the four step operations
-KERNEL_NAMES = {"sq32_fill": "k_fill<0,", "sq64_fill": "k_fill<2,", "fused_f32_sum": "k_reduce<1,",
-                "fused_f64_sum": "k_reduce<3,"}
+# rocprofv3 kernel names (spaces and namespace removed) of the four step
+# operations: the unit-step instantiations of the fill and reduce templates
+KERNEL_NAMES = {"sq32_fill": r"k_fill<0,\d+,false>", "sq64_fill": r"k_fill<2,\d+,false>",
+                "fused_f32_sum": r"k_reduce<1,\d+,false>", "fused_f64_sum": r"k_reduce<3,\d+,false>"}
 
 
 def kernel_source_sha() -> str:
@@ -69,14 +72,15 @@ def traffic_from_pmc(fetch_csv: str, write_csv: str, log2n: int) -> dict:
     counter reads for the plain 4 GiB device copy that --calib-copy runs
     first (the largest __amd_rocclr_copyBuffer dispatch)."""
     import csv
+    import re
 
     def load(path):
         rows = list(csv.DictReader(open(path)))
         copy = max((r for r in rows if "copyBuffer" in r["Kernel_Name"]), key=lambda r: float(r["Counter_Value"]))
         per = {}
-        for name, pref in KERNEL_NAMES.items():
+        for name, pat in KERNEL_NAMES.items():
             vals = [float(r["Counter_Value"]) * 1024 for r in rows
-                    if pref in r["Kernel_Name"].replace(" ", "").replace("(anonymousnamespace)::", "")]
+                    if re.search(pat, r["Kernel_Name"].replace(" ", "").replace("(anonymousnamespace)::", ""))]
             per[name] = sum(vals) / len(vals) if vals else None
         return float(copy["Counter_Value"]) * 1024, per
 
@@ -102,6 +106,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--log2n", type=int, default=32)
     p.add_argument("--no-extras", action="store_true")
+    p.add_argument("--extras", default="split,modes,batch,serving",
+                   help="comma list of extra measurements after the step (split, modes, batch, serving)")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--calib-copy", action="store_true",
                    help="run a plain 4 GiB device copy first (scales HBM byte counters)")
@@ -110,7 +116,7 @@ def parse():
     return p.parse_args()
 
 
-def cpu_baseline(key: int, ctr0: int, log2_sample: int = 30) -> dict:
+def cpu_baseline(key: int, ctr0: int, log2_sample: int = 31) -> dict:
     """The oracle as it stands, on the host cores, over the same four
     operations for 2^log2_sample counters each (same key and start).  The
     fills write into a reused host buffer of 2^26 elements, one chunk at a
@@ -197,6 +203,57 @@ def split_words(sq, torch, key: int, ctr0: int, n: int, per_op_ms: dict) -> dict
     r["u32x2_fill"]["vs_sq32_fill"] = round(per_op_ms["sq32_fill"] / r["u32x2_fill"]["ms"], 3)
     r["fused_f32x2_sum"]["vs_fused_f32_sum"] = round(per_op_ms["fused_f32_sum"] / r["fused_f32x2_sum"]["ms"], 3)
     del out
+    torch.cuda.empty_cache()
+    return r
+
+
+def _event_ms(torch, fn, reps: int = 10, warm: int = 2) -> float:
+    """Mean duration of fn() from HIP events on the current stream."""
+    for _ in range(warm):
+        fn()
+    evs = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        evs.append((a, b))
+    torch.cuda.synchronize()
+    return sum(a.elapsed_time(b) for a, b in evs) / len(evs)
+
+
+def counter_modes(sq, torch, key: int, ctr0: int, n: int, per_op_ms: dict) -> dict:
+    """The counter modes of Section 4 beside the unit-step kernels: a squares32
+    fill and F32 sum over n outputs whose counters are 3 apart, key-counter
+    mode over 2^28 device-generated distinct-digit keys at counter 0 (U32 and
+    U64 outputs; bytes counted are the 8-byte key read plus the output
+    written), and the key generator itself."""
+    step = 3
+    out = torch.empty(n, dtype=torch.uint32, device="cuda")
+    res, ws = sq.result_tensor(), sq.reduce_workspace(n)
+    r = {}
+    ms = _event_ms(torch, lambda: sq.fill_strided(sq.U32, key, ctr0, step, n, out=out))
+    gbs = 4 * n / (ms * 1e-3) / 1e9
+    r["strided_u32_fill"] = {"step": step, "n": n, "ms": round(ms, 4), "gnum_s": round(n / (ms * 1e-3) / 1e9, 1),
+                             "gb_s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                             "vs_unit_step": round(per_op_ms["sq32_fill"] / ms, 3)}
+    ms = _event_ms(torch, lambda: sq.reduce_strided_async(sq.F32, key, ctr0, step, n, res, ws))
+    r["strided_f32_sum"] = {"step": step, "n": n, "ms": round(ms, 4), "gnum_s": round(n / (ms * 1e-3) / 1e9, 1),
+                            "vs_unit_step": round(per_op_ms["fused_f32_sum"] / ms, 3)}
+    del out
+    torch.cuda.empty_cache()
+    m = 1 << 28
+    keys = torch.empty(m, dtype=torch.uint64, device="cuda")
+    gen_key = 0x9E3779B97F4A7C15
+    ms = _event_ms(torch, lambda: sq.make_keys(gen_key, 0, m, out=keys), reps=5)
+    r["make_keys"] = {"m": m, "ms": round(ms, 4), "gkeys_s": round(m / (ms * 1e-3) / 1e9, 1)}
+    kout = torch.empty(m, dtype=torch.uint64, device="cuda")
+    for name, kind, W in (("key_counter_u32", sq.U32, 4), ("key_counter_u64", sq.U64, 8)):
+        ms = _event_ms(torch, lambda: sq.fill_keys(kind, 0, keys, out=kout))
+        gbs = (8 + W) * m / (ms * 1e-3) / 1e9
+        r[name] = {"m": m, "ctr": 0, "ms": round(ms, 4), "gnum_s": round(m / (ms * 1e-3) / 1e9, 1),
+                   "gb_s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    del keys, kout
     torch.cuda.empty_cache()
     return r
 
@@ -336,15 +393,17 @@ def main() -> int:
     }
     del out32, out64
     torch.cuda.empty_cache()
-    if not args.no_extras:
+    extras = set() if args.no_extras else set(args.extras.split(","))
+    if "split" in extras:
         line["split_words"] = split_words(sq, torch, key, ctr0, n, per_op_ms)
+    if "modes" in extras:
+        line["counter_modes"] = counter_modes(sq, torch, key, ctr0, n, per_op_ms)
+    if "batch" in extras:
         line["batch"] = batch_speedup(sq, torch)
-        try:
-            from paper_2004_06278_amd import serve_bench
+    if "serving" in extras:
+        from paper_2004_06278_amd import serve_bench
 
-            line["serving"] = serve_bench.run_short(sq, torch)
-        except ImportError:
-            pass
+        line["serving"] = serve_bench.run_short(sq, torch)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(key, ctr0)
     print(json.dumps(line), flush=True)

@@ -160,6 +160,61 @@ int sq_reduce_cfg(sq_kind kind, uint64_t key, uint64_t ctr0, uint64_t n, sq_sum_
                   void *ws, size_t ws_bytes, const sq_launch_cfg *cfg, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Counter increments other than one (Section 4 lists tests of such
+ * increments).  Element i is the output of `kind` at counter
+ *   ctr0 + i*step (mod 2^64)
+ * for U32/F32/U64/F64, and for the split kinds word (i & 1) of squares64 at
+ * counter ctr0 + (i/2)*step.  Each counter's second Weyl term stays
+ * (ctr+1)*key: the step chooses which counters are visited, the generator
+ * is unchanged.  step = 1 gives exactly sq_fill / sq_reduce, step = 0
+ * repeats counter ctr0, step = 2^64 - 1 runs the counters backwards.
+ * Arguments, alignment, ownership and errors as for sq_fill (fill) and
+ * sq_reduce (sum; the sum covers the same n outputs the fill writes).
+ * ------------------------------------------------------------------------ */
+int sq_fill_strided(sq_kind kind, uint64_t key, uint64_t ctr0, uint64_t step, uint64_t n,
+                    void *out, void *stream);
+int sq_fill_strided_cfg(sq_kind kind, uint64_t key, uint64_t ctr0, uint64_t step, uint64_t n,
+                        void *out, const sq_launch_cfg *cfg, void *stream);
+int sq_reduce_strided(sq_kind kind, uint64_t key, uint64_t ctr0, uint64_t step, uint64_t n,
+                      sq_sum_result *out, void *ws, size_t ws_bytes, void *stream);
+int sq_reduce_strided_cfg(sq_kind kind, uint64_t key, uint64_t ctr0, uint64_t step, uint64_t n,
+                          sq_sum_result *out, void *ws, size_t ws_bytes,
+                          const sq_launch_cfg *cfg, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Key-counter mode (Section 4): the counter is fixed and the key varies.
+ *   out[j] = f(ctr, keys[j]),  j in [0, m)
+ * for kinds U32, F32, U64, F64 (other kinds: SQ_EINVAL).  `keys` is a DEVICE
+ * array of m keys (8-byte aligned, else SQ_EALIGN), read once; `out` a device
+ * buffer of m elements aligned to the element size.  When both are 16-byte
+ * aligned the kernel reads and writes whole 16-byte vectors; otherwise it
+ * works one element per lane.  m == 0 returns SQ_OK without a launch.  The
+ * _cfg variant takes `block` and `grid_per_cu` from cfg (validated as a fill
+ * configuration; `unroll`, `xcd_map` and `tile_log2` are ignored).
+ * ------------------------------------------------------------------------ */
+int sq_fill_keys(sq_kind kind, uint64_t ctr, const uint64_t *keys, uint64_t m, void *out,
+                 void *stream);
+int sq_fill_keys_cfg(sq_kind kind, uint64_t ctr, const uint64_t *keys, uint64_t m, void *out,
+                     const sq_launch_cfg *cfg, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Distinct-digit keys on the device (Section 3, Discussion: a key's upper 8
+ * hex digits are mutually different, so are its lower 8, and the digits
+ * are random).  Key j depends only on (gen_key, ctr0, j):
+ *   half h (0: upper 32 bits, 1: lower) takes r = squares64(ctr0 + 2j + h,
+ *   gen_key) mod 2^64 counters, u = floor(r * N / 2^64) with
+ *   N = 16*15*...*9 = 518918400, and the digits of a partial Fisher-Yates
+ *   shuffle of 0..15 whose step i (i = 0..7) takes the digit at position
+ *   i + (u mod (16 - i)) and then sets u = u div (16 - i); the first digit
+ *   taken is the most significant.
+ * So keys[ctr0 .. ] windows compose: sq_make_keys(g, c + 2k, ...) yields keys
+ * k, k+1, ... of sq_make_keys(g, c, ...).  `keys` is a device array of m
+ * uint64 (8-byte aligned); m <= 2^62.  gen_key should itself be a
+ * distinct-digit key.
+ * ------------------------------------------------------------------------ */
+int sq_make_keys(uint64_t gen_key, uint64_t ctr0, uint64_t m, uint64_t *keys, void *stream);
+
+/* ------------------------------------------------------------------------
  * Ragged batch: m streams in one launch (more keys give more streams,
  * Section 3).  Stream s writes lens[s] outputs of kind kinds[s] from counter
  * ctr0s[s] under keys[s] at byte offset offs[s] of the arena `out` of

@@ -17,7 +17,13 @@
  * worked by hand, the ctr = 0 reduction, the identity hi32(squares64) ==
  * squares32, the Weyl identity, counter wrap, a bit-balance screen, and a
  * mutation battery showing each plausible transcription mistake fails one
- * of them.
+ * of them.  The counter modes are pinned against the unit-step fill
+ * (subsampling, one-element fills) and special steps; the key generator by
+ * hand-worked decodes, an independently written inverse and the digit
+ * property.
+ *
+ * Parity unpinned: equality with the author's own binary and key utility,
+ * which are not available.
  */
 #include <stdint.h>
 #include <stddef.h>

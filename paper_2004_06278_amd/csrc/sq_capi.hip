@@ -69,7 +69,7 @@ extern "C" {
 
 const char* sq_last_error(void) { return g_err.c_str(); }
 
-int sq_version(void) { return 10000; }
+int sq_version(void) { return 10100; }
 
 int sq_init(void) {
   SQ_INIT_OR_RETURN();
@@ -125,10 +125,98 @@ int sq_uniform_f32x2(uint64_t key, uint64_t ctr0, uint64_t n, float* out, void* 
   return sq_fill(SQ_F32X2, key, ctr0, n, out, stream);
 }
 
+// ---------------------------------------------------------------- counter increments other than one
+int sq_fill_strided_cfg(sq_kind kind, uint64_t key, uint64_t ctr0, uint64_t step, uint64_t n, void* out,
+                        const sq_launch_cfg* cfg, void* stream) {
+  int rc = check_fill(kind, n, out);
+  if (rc != SQ_OK || n == 0) return rc;
+  if (cfg == nullptr || !cfg_valid(SQ_OP_FILL, *cfg)) return fail(SQ_EINVAL, "invalid fill launch configuration");
+  SQ_INIT_OR_RETURN();
+  hipError_t e = launch_fill(kind, key, ctr0, n, out, *cfg, (hipStream_t)stream, step);
+  return e == hipSuccess ? SQ_OK : fail_hip(e, "strided fill launch");
+}
+
+int sq_fill_strided(sq_kind kind, uint64_t key, uint64_t ctr0, uint64_t step, uint64_t n, void* out,
+                    void* stream) {
+  int rc = check_fill(kind, n, out);
+  if (rc != SQ_OK || n == 0) return rc;
+  SQ_INIT_OR_RETURN();
+  const sq_launch_cfg cfg = tuned_cfg(SQ_OP_FILL, kind, n);
+  return sq_fill_strided_cfg(kind, key, ctr0, step, n, out, &cfg, stream);
+}
+
+// ---------------------------------------------------------------- key-counter mode
+// Measured on MI355X over 2^29 keys: 512 threads and 64 workgroups per CU
+// stream keys in and outputs out at the rate of a plain device copy.
+static sq_launch_cfg keys_default_cfg() {
+  sq_launch_cfg c{};
+  c.block = 512;
+  c.unroll = 4;  // unused
+  c.grid_per_cu = 64;
+  c.xcd_map = 0;
+  c.tile_log2 = 16;
+  return c;
+}
+
+int sq_fill_keys_cfg(sq_kind kind, uint64_t ctr, const uint64_t* keys, uint64_t m, void* out,
+                     const sq_launch_cfg* cfg, void* stream) {
+  if (kind != SQ_U32 && kind != SQ_F32 && kind != SQ_U64 && kind != SQ_F64)
+    return fail(SQ_EINVAL, "key-counter mode takes kinds U32, F32, U64 and F64, not " + std::to_string((int)kind));
+  if (m == 0) return SQ_OK;
+  if (keys == nullptr || out == nullptr) return fail(SQ_EINVAL, "null keys or output pointer with m > 0");
+  if (((uintptr_t)keys & 7) != 0) return fail(SQ_EALIGN, "keys must be 8-byte aligned");
+  if (((uintptr_t)out & (uintptr_t)(kind_bytes(kind) - 1)) != 0)
+    return fail(SQ_EALIGN, "output pointer not aligned to " + std::to_string(kind_bytes(kind)) + " bytes");
+  if (cfg == nullptr || !cfg_valid(SQ_OP_FILL, *cfg)) return fail(SQ_EINVAL, "invalid launch configuration");
+  SQ_INIT_OR_RETURN();
+  hipError_t e = launch_keys(kind, ctr, keys, m, out, *cfg, (hipStream_t)stream);
+  return e == hipSuccess ? SQ_OK : fail_hip(e, "key-counter launch");
+}
+
+int sq_fill_keys(sq_kind kind, uint64_t ctr, const uint64_t* keys, uint64_t m, void* out, void* stream) {
+  const sq_launch_cfg cfg = keys_default_cfg();
+  return sq_fill_keys_cfg(kind, ctr, keys, m, out, &cfg, stream);
+}
+
+// ---------------------------------------------------------------- key generation
+int sq_make_keys(uint64_t gen_key, uint64_t ctr0, uint64_t m, uint64_t* keys, void* stream) {
+  if (m == 0) return SQ_OK;
+  if (keys == nullptr) return fail(SQ_EINVAL, "null keys pointer with m > 0");
+  if (((uintptr_t)keys & 7) != 0) return fail(SQ_EALIGN, "keys must be 8-byte aligned");
+  if (m > (1ull << 62)) return fail(SQ_EINVAL, "m > 2^62: key j uses counters ctr0 + 2j and ctr0 + 2j + 1");
+  SQ_INIT_OR_RETURN();
+  sq_launch_cfg cfg = keys_default_cfg();
+  cfg.grid_per_cu = 16;
+  hipError_t e = launch_make_keys(gen_key, ctr0, m, keys, cfg, (hipStream_t)stream);
+  return e == hipSuccess ? SQ_OK : fail_hip(e, "key generation launch");
+}
+
 // ---------------------------------------------------------------- reduce
 size_t sq_reduce_workspace_bytes(uint64_t n) {
   (void)n;
   return 16ull * kReduceMaxParts;
+}
+
+int sq_reduce_strided_cfg(sq_kind kind, uint64_t key, uint64_t ctr0, uint64_t step, uint64_t n,
+                          sq_sum_result* out, void* ws, size_t ws_bytes, const sq_launch_cfg* cfg, void* stream) {
+  if (kind_bytes(kind) == 0) return fail(SQ_EINVAL, "unknown kind " + std::to_string((int)kind));
+  if (out == nullptr || ws == nullptr) return fail(SQ_EINVAL, "null result or workspace pointer");
+  if (((uintptr_t)out & 7) != 0 || ((uintptr_t)ws & 15) != 0)
+    return fail(SQ_EALIGN, "result must be 8-byte and workspace 16-byte aligned");
+  if (ws_bytes < sq_reduce_workspace_bytes(n))
+    return fail(SQ_ENOMEM, "reduce workspace smaller than sq_reduce_workspace_bytes()");
+  if (cfg == nullptr || !cfg_valid(SQ_OP_REDUCE, *cfg)) return fail(SQ_EINVAL, "invalid reduce launch configuration");
+  SQ_INIT_OR_RETURN();
+  hipError_t e = launch_reduce(kind, key, ctr0, n, out, ws, *cfg, (hipStream_t)stream, step);
+  return e == hipSuccess ? SQ_OK : fail_hip(e, "reduce launch");
+}
+
+int sq_reduce_strided(sq_kind kind, uint64_t key, uint64_t ctr0, uint64_t step, uint64_t n, sq_sum_result* out,
+                      void* ws, size_t ws_bytes, void* stream) {
+  if (kind_bytes(kind) == 0) return fail(SQ_EINVAL, "unknown kind " + std::to_string((int)kind));
+  SQ_INIT_OR_RETURN();
+  const sq_launch_cfg cfg = tuned_cfg(SQ_OP_REDUCE, kind, n);
+  return sq_reduce_strided_cfg(kind, key, ctr0, step, n, out, ws, ws_bytes, &cfg, stream);
 }
 
 int sq_reduce_cfg(sq_kind kind, uint64_t key, uint64_t ctr0, uint64_t n, sq_sum_result* out, void* ws,

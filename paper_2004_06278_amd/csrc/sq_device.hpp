@@ -164,6 +164,34 @@ __device__ __forceinline__ u32x4 gen_vec(uint64_t y0, uint64_t key) {
   return o;
 }
 
+// The same sixteen bytes when consecutive outputs are `step` counters apart
+// (Section 4 tests increments other than one): the first Weyl terms advance
+// by dkey = step*key, and each output's second term is its own first term
+// plus key, since z(c) = (c+1)*key no longer equals y of the next output.
+template <int K>
+__device__ __forceinline__ u32x4 gen_vec_strided(uint64_t y0, uint64_t key, uint64_t dkey) {
+  u32x4 o;
+  if constexpr (Kind<K>::SPLIT) {
+    const uint64_t y1 = y0 + dkey;
+    uint32_t a, b, c, d;
+    split_pair<K>(y0, y0 + key, a, b);
+    split_pair<K>(y1, y1 + key, c, d);
+    o.x = a; o.y = b; o.z = c; o.w = d;
+  } else if constexpr (Kind<K>::W == 4) {
+    const uint64_t y1 = y0 + dkey, y2 = y1 + dkey, y3 = y2 + dkey;
+    o.x = (uint32_t)gen_bits<K>(y0, y0 + key);
+    o.y = (uint32_t)gen_bits<K>(y1, y1 + key);
+    o.z = (uint32_t)gen_bits<K>(y2, y2 + key);
+    o.w = (uint32_t)gen_bits<K>(y3, y3 + key);
+  } else {
+    const uint64_t y1 = y0 + dkey;
+    const uint64_t a = gen_bits<K>(y0, y0 + key), b = gen_bits<K>(y1, y1 + key);
+    o.x = (uint32_t)a; o.y = (uint32_t)(a >> 32);
+    o.z = (uint32_t)b; o.w = (uint32_t)(b >> 32);
+  }
+  return o;
+}
+
 // Counter offset of element i of a range (split kinds: two elements per
 // counter).
 template <int K>
@@ -171,11 +199,13 @@ __device__ __forceinline__ uint64_t elem_ctr(uint64_t i) {
   return Kind<K>::SPLIT ? i >> 1 : i;
 }
 
-// Writes element i of a range that starts at counter ctr0 (element store,
-// for heads and tails); p is the element's address.
+// Writes element i of a range that starts at counter ctr0 and visits every
+// step-th counter (element store, for heads and tails); p is the element's
+// address.
 template <int K>
-__device__ __forceinline__ void store_elem(unsigned char* p, uint64_t ctr0, uint64_t i, uint64_t key) {
-  const uint64_t y = (ctr0 + elem_ctr<K>(i)) * key;
+__device__ __forceinline__ void store_elem(unsigned char* p, uint64_t ctr0, uint64_t i, uint64_t key,
+                                           uint64_t step = 1) {
+  const uint64_t y = (ctr0 + elem_ctr<K>(i) * step) * key;
   if constexpr (Kind<K>::SPLIT) {
     uint32_t lo, hi;
     split_pair<K>(y, y + key, lo, hi);

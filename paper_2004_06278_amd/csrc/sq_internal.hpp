@@ -40,12 +40,22 @@ sq_launch_cfg default_cfg(sq_op op, int kind, uint64_t n);
 sq_launch_cfg tuned_cfg(sq_op op, int kind, uint64_t n);  // table lookup (default if unset)
 
 // ---------------------------------------------------------------- launches
+// step: counter increment between consecutive outputs (1 for the plain
+// fill and reduce).
 hipError_t launch_fill(int kind, uint64_t key, uint64_t ctr0, uint64_t n, void* out,
-                       const sq_launch_cfg& cfg, hipStream_t s);
+                       const sq_launch_cfg& cfg, hipStream_t s, uint64_t step = 1);
 
 constexpr uint32_t kReduceMaxParts = 65536;
 hipError_t launch_reduce(int kind, uint64_t key, uint64_t ctr0, uint64_t n, sq_sum_result* out,
-                         void* ws, const sq_launch_cfg& cfg, hipStream_t s);
+                         void* ws, const sq_launch_cfg& cfg, hipStream_t s, uint64_t step = 1);
+
+// Key-counter mode: out[j] = kind's output at counter ctr under keys[j].
+hipError_t launch_keys(int kind, uint64_t ctr, const uint64_t* keys, uint64_t m, void* out,
+                       const sq_launch_cfg& cfg, hipStream_t s);
+
+// Distinct-digit keys from a counter range of squares64 under gen_key.
+hipError_t launch_make_keys(uint64_t gen_key, uint64_t ctr0, uint64_t m, uint64_t* keys,
+                            const sq_launch_cfg& cfg, hipStream_t s);
 
 // Descriptor arrays of a ragged batch (device pointers).
 struct BatchDesc {

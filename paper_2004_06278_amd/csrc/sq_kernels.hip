@@ -29,8 +29,10 @@ struct FillArgs {
   unsigned char* out;   // address of element 0 (element-aligned)
   uint64_t nvec;        // full 16-byte vectors in the aligned body
   uint64_t nchunks;     // ceil(nvec / (block * U))
-  uint64_t y_body;      // first Weyl term of the body: (ctr0 + counter offset of head) * key
-  uint64_t ekey;        // CPV * key: Weyl step from one vector to the next
+  uint64_t step;        // counter increment between consecutive outputs
+  uint64_t dkey;        // step * key: first-Weyl-term increment per counter visited
+  uint64_t y_body;      // first Weyl term of the body: (ctr0 + step * counter offset of head) * key
+  uint64_t ekey;        // CPV * dkey: Weyl step from one vector to the next
   uint32_t head;        // elements before the 1 KiB aligned body (< 1024 / W)
   uint32_t tail;        // elements after the last full vector (0..3)
   uint32_t xcd_map;     // chunk order, see sq_launch_cfg
@@ -45,14 +47,22 @@ __device__ __forceinline__ void fill_edges(const FillArgs& a) {
   if (blockIdx.x != 0) return;
   for (uint32_t t = threadIdx.x; t < a.head + a.tail; t += blockDim.x) {
     const uint64_t i = t < a.head ? (uint64_t)t : a.head + a.nvec * E + (t - a.head);
-    store_elem<K>(a.out + i * W, a.ctr0, i, a.key);
+    store_elem<K>(a.out + i * W, a.ctr0, i, a.key, a.step);
   }
+}
+
+// One 16-byte vector of the body: unit counter increments share each
+// counter's second Weyl term with the next counter's first.
+template <int K, bool S>
+__device__ __forceinline__ u32x4 body_vec(const FillArgs& a, uint64_t y) {
+  if constexpr (S) return gen_vec_strided<K>(y, a.key, a.dkey);
+  else return gen_vec<K>(y, a.key);
 }
 
 // Chunk c covers vectors [c*B*U, (c+1)*B*U) of the body; lane tid writes
 // vectors c*B*U + u*B + tid, u < U (so each store instruction of a wave
 // covers 1 KiB contiguous, and a workgroup's U stores cover B*U*16 bytes).
-template <int K, int U>
+template <int K, int U, bool S>
 __device__ __forceinline__ void fill_chunk(const FillArgs& a, uint64_t c) {
   constexpr int W = Kind<K>::W;
   const uint32_t B = blockDim.x, tid = threadIdx.x;
@@ -66,7 +76,7 @@ __device__ __forceinline__ void fill_chunk(const FillArgs& a, uint64_t c) {
   if ((c + 1) * B * U <= a.nvec) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      p[(uint64_t)u * B] = gen_vec<K>(y, a.key);
+      p[(uint64_t)u * B] = body_vec<K, S>(a, y);
       y += step;
       // one vector's chains at a time: keeps VGPR use low (occupancy hides
       // the latency of the dependent rounds better than interleaving)
@@ -75,19 +85,19 @@ __device__ __forceinline__ void fill_chunk(const FillArgs& a, uint64_t c) {
   } else {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (v0 + (uint64_t)u * B < a.nvec) p[(uint64_t)u * B] = gen_vec<K>(y, a.key);
+      if (v0 + (uint64_t)u * B < a.nvec) p[(uint64_t)u * B] = body_vec<K, S>(a, y);
       y += step;
       __builtin_amdgcn_sched_barrier(0);
     }
   }
 }
 
-template <int K, int U>
+template <int K, int U, bool S>
 __global__ __launch_bounds__(1024) void k_fill(FillArgs a) {
   fill_edges<K>(a);
   if (a.xcd_map == 0) {
 #pragma unroll 1
-    for (uint64_t c = blockIdx.x; c < a.nchunks; c += gridDim.x) fill_chunk<K, U>(a, c);
+    for (uint64_t c = blockIdx.x; c < a.nchunks; c += gridDim.x) fill_chunk<K, U, S>(a, c);
   } else {
     // Workgroups are dispatched round-robin over the 8 XCDs; give XCD r the
     // r-th contiguous eighth of the chunks (gridDim.x is a multiple of 8).
@@ -96,24 +106,25 @@ __global__ __launch_bounds__(1024) void k_fill(FillArgs a) {
     const uint64_t beg = r * per;
     const uint64_t end = beg + per < a.nchunks ? beg + per : a.nchunks;
 #pragma unroll 1
-    for (uint64_t c = beg + local; c < end; c += gx) fill_chunk<K, U>(a, c);
+    for (uint64_t c = beg + local; c < end; c += gx) fill_chunk<K, U, S>(a, c);
   }
 }
 
 typedef void (*FillKernel)(FillArgs);
-template <int K>
+template <int K, bool S>
 FillKernel fill_kernel_for(uint32_t unroll) {
-  return unroll == 4 ? k_fill<K, 4> : k_fill<K, 8>;
+  return unroll == 4 ? k_fill<K, 4, S> : k_fill<K, 8, S>;
 }
 
+template <bool S>
 FillKernel fill_kernel(int kind, uint32_t unroll) {
   switch (kind) {
-    case SQ_U32: return fill_kernel_for<0>(unroll);
-    case SQ_F32: return fill_kernel_for<1>(unroll);
-    case SQ_U64: return fill_kernel_for<2>(unroll);
-    case SQ_F64: return fill_kernel_for<3>(unroll);
-    case SQ_U32X2: return fill_kernel_for<4>(unroll);
-    default: return fill_kernel_for<5>(unroll);
+    case SQ_U32: return fill_kernel_for<0, S>(unroll);
+    case SQ_F32: return fill_kernel_for<1, S>(unroll);
+    case SQ_U64: return fill_kernel_for<2, S>(unroll);
+    case SQ_F64: return fill_kernel_for<3, S>(unroll);
+    case SQ_U32X2: return fill_kernel_for<4, S>(unroll);
+    default: return fill_kernel_for<5, S>(unroll);
   }
 }
 
@@ -121,10 +132,21 @@ FillKernel fill_kernel(int kind, uint32_t unroll) {
 struct ReduceArgs {
   uint64_t key;
   uint64_t ctr0;
+  uint64_t dkey;         // step * key: first-Weyl-term increment per counter visited
+  uint64_t y0;           // (ctr0 + per * step * thread) * key is y0 + thread * ythread
+  uint64_t ythread;      // per * dkey
   uint64_t n;            // counters to sum (split kinds: pairs of outputs)
   uint64_t per;          // counters per thread (contiguous)
   uint64_t* partials;    // 2 x u64 per workgroup
 };
+
+// Advances the first Weyl term past the counter whose second term is z: by
+// unit counter increments that is z itself, else y + step*key.
+template <bool S>
+__device__ __forceinline__ uint64_t next_y(uint64_t y, uint64_t z, uint64_t dkey) {
+  if constexpr (S) return y + dkey;
+  else return z;
+}
 
 __device__ __forceinline__ void add128(uint64_t& lo, uint64_t& hi, uint64_t v_lo, uint64_t v_hi) {
   const uint64_t s = lo + v_lo;
@@ -157,7 +179,7 @@ __device__ __forceinline__ void block_sum128(uint64_t& lo, uint64_t& hi) {
 // Each thread sums its own contiguous run of counters.  The integer terms
 // are accumulated exactly: in 64 bits over runs short enough not to
 // overflow (FLUSH terms), then into a 128-bit total.
-template <int K, int U>
+template <int K, int U, bool S>
 __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a) {
   const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   uint64_t cnt = 0;
@@ -165,8 +187,8 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a) {
     const uint64_t begin = t * a.per;
     cnt = a.n - begin < a.per ? a.n - begin : a.per;
   }
-  const uint64_t key = a.key;
-  uint64_t y = (a.ctr0 + t * a.per) * key;
+  const uint64_t key = a.key, dkey = a.dkey;
+  uint64_t y = a.y0 + t * a.ythread;
   uint64_t lo = 0, hi = 0;
   if constexpr (K == 2) {
     // 64-bit terms: a 64-bit partial plus a 32-bit count of its carries,
@@ -185,7 +207,7 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a) {
           unsigned long long c;
           s = __builtin_addcll(s, sum_term<K>(y, z), 0ull, &c);
           carries += (uint32_t)c;
-          y = z;
+          y = next_y<S>(y, z, dkey);
         }
       }
       for (; j < len; ++j) {
@@ -193,7 +215,7 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a) {
         unsigned long long c;
         s = __builtin_addcll(s, sum_term<K>(y, z), 0ull, &c);
         carries += (uint32_t)c;
-        y = z;
+        y = next_y<S>(y, z, dkey);
       }
       add128(lo, hi, s, carries);
       i += len;
@@ -219,13 +241,13 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a) {
         for (int u = 0; u < U; ++u) {
           const uint64_t z = y + key;
           s += (Part)sum_term<K>(y, z);
-          y = z;
+          y = next_y<S>(y, z, dkey);
         }
       }
       for (; j < len; ++j) {
         const uint64_t z = y + key;
         s += (Part)sum_term<K>(y, z);
-        y = z;
+        y = next_y<S>(y, z, dkey);
       }
       add128(lo, hi, (uint64_t)s, 0);
       i += len;
@@ -274,23 +296,24 @@ __global__ __launch_bounds__(256) void k_reduce_final(const uint64_t* partials, 
 }
 
 typedef void (*ReduceKernel)(ReduceArgs);
-template <int K>
+template <int K, bool S>
 ReduceKernel reduce_kernel_for(uint32_t unroll) {
   switch (unroll) {
-    case 1: return k_reduce<K, 1>;
-    case 2: return k_reduce<K, 2>;
-    default: return k_reduce<K, 4>;
+    case 1: return k_reduce<K, 1, S>;
+    case 2: return k_reduce<K, 2, S>;
+    default: return k_reduce<K, 4, S>;
   }
 }
 
+template <bool S>
 ReduceKernel reduce_kernel(int kind, uint32_t unroll) {
   switch (kind) {
-    case SQ_U32: return reduce_kernel_for<0>(unroll);
-    case SQ_F32: return reduce_kernel_for<1>(unroll);
-    case SQ_U64: return reduce_kernel_for<2>(unroll);
-    case SQ_F64: return reduce_kernel_for<3>(unroll);
-    case SQ_U32X2: return reduce_kernel_for<4>(unroll);
-    default: return reduce_kernel_for<5>(unroll);
+    case SQ_U32: return reduce_kernel_for<0, S>(unroll);
+    case SQ_F32: return reduce_kernel_for<1, S>(unroll);
+    case SQ_U64: return reduce_kernel_for<2, S>(unroll);
+    case SQ_F64: return reduce_kernel_for<3, S>(unroll);
+    case SQ_U32X2: return reduce_kernel_for<4, S>(unroll);
+    default: return reduce_kernel_for<5, S>(unroll);
   }
 }
 
@@ -442,6 +465,118 @@ __global__ __launch_bounds__(1024) void k_batch_fill(sqi::BatchDesc d, uint32_t 
   }
 }
 
+// ============================================================== key-counter mode
+// Counter fixed, keys varying (the key-counter usage of Section 4): output j
+// comes from keys[j].  Each lane reads 16 / W keys (32 or 16 bytes) and
+// writes their outputs as one 16-byte vector, so the kernel streams keys in
+// and outputs out at HBM rate; the generator itself is the same as the
+// fill's.
+typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+
+struct KeysArgs {
+  const uint64_t* keys;
+  unsigned char* out;
+  uint64_t m;
+  uint64_t ctr;
+  uint64_t nvec;  // full 16-byte output vectors (vector kernel)
+};
+
+template <int K>
+__device__ __forceinline__ uint64_t keyed_bits(uint64_t ctr, uint64_t key) {
+  const uint64_t y = ctr * key;
+  return gen_bits<K>(y, y + key);
+}
+
+template <int K>
+__device__ __forceinline__ void keyed_store(const KeysArgs& a, uint64_t j) {
+  const uint64_t v = keyed_bits<K>(a.ctr, a.keys[j]);
+  if constexpr (Kind<K>::W == 4) ((uint32_t*)a.out)[j] = (uint32_t)v;
+  else ((uint64_t*)a.out)[j] = v;
+}
+
+// keys and out 16-byte aligned: vector loads and stores, tail by workgroup 0.
+template <int K>
+__global__ __launch_bounds__(1024) void k_keys_vec(KeysArgs a) {
+  constexpr int E = 16 / Kind<K>::W;
+  const u64x2* kp = (const u64x2*)a.keys;
+  u32x4* op = (u32x4*)a.out;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+#pragma unroll 1
+  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < a.nvec; v += stride) {
+    u32x4 o;
+    if constexpr (E == 4) {
+      const u64x2 k0 = kp[2 * v], k1 = kp[2 * v + 1];
+      o.x = (uint32_t)keyed_bits<K>(a.ctr, k0.x);
+      o.y = (uint32_t)keyed_bits<K>(a.ctr, k0.y);
+      o.z = (uint32_t)keyed_bits<K>(a.ctr, k1.x);
+      o.w = (uint32_t)keyed_bits<K>(a.ctr, k1.y);
+    } else {
+      const u64x2 k0 = kp[v];
+      const uint64_t b0 = keyed_bits<K>(a.ctr, k0.x), b1 = keyed_bits<K>(a.ctr, k0.y);
+      o.x = (uint32_t)b0; o.y = (uint32_t)(b0 >> 32);
+      o.z = (uint32_t)b1; o.w = (uint32_t)(b1 >> 32);
+    }
+    op[v] = o;
+  }
+  if (blockIdx.x == 0 && threadIdx.x < a.m - a.nvec * E) keyed_store<K>(a, a.nvec * E + threadIdx.x);
+}
+
+// Any element-aligned keys/out: one key per lane.
+template <int K>
+__global__ __launch_bounds__(1024) void k_keys_elem(KeysArgs a) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+#pragma unroll 1
+  for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < a.m; j += stride) keyed_store<K>(a, j);
+}
+
+typedef void (*KeysKernel)(KeysArgs);
+KeysKernel keys_kernel(int kind, bool vec) {
+  switch (kind) {
+    case SQ_U32: return vec ? k_keys_vec<0> : k_keys_elem<0>;
+    case SQ_F32: return vec ? k_keys_vec<1> : k_keys_elem<1>;
+    case SQ_U64: return vec ? k_keys_vec<2> : k_keys_elem<2>;
+    default: return vec ? k_keys_vec<3> : k_keys_elem<3>;
+  }
+}
+
+// ============================================================== key generation
+// Distinct-digit keys (Section 3, Discussion: the upper 8 hex digits mutually
+// different, the lower 8 too, chosen at random).  Half h of key j draws
+// r = squares64(ctr0 + 2j + h) under gen_key, scales it to an index
+// u = floor(r * N / 2^64) over the N = 16!/8! ordered choices of 8 digits,
+// and reads u's mixed-radix digits (radix 16, 15, ..., 9) as the choices of a
+// partial Fisher-Yates shuffle of 0..15.  The 16-digit list lives in one
+// 64-bit register, one digit per nibble.
+constexpr uint64_t kKeyChoices = 518918400ull;  // 16 * 15 * ... * 9
+
+__device__ __forceinline__ uint32_t digits_half(uint64_t r) {
+  uint32_t u = (uint32_t)__umul64hi(r, kKeyChoices);  // < 2^29
+  uint64_t pool = 0xFEDCBA9876543210ull;              // nibble p holds digit p
+  uint32_t half = 0;
+#pragma unroll
+  for (uint32_t i = 0; i < 8; ++i) {
+    const uint32_t radix = 16 - i;
+    const uint32_t q = i + u % radix;
+    u /= radix;
+    const uint64_t dq = (pool >> (4 * q)) & 15, di = (pool >> (4 * i)) & 15;
+    // swap nibbles i and q (a no-op when q == i)
+    pool ^= ((dq ^ di) << (4 * i)) | ((dq ^ di) << (4 * q));
+    half = (half << 4) | (uint32_t)dq;
+  }
+  return half;
+}
+
+__global__ __launch_bounds__(256) void k_make_keys(uint64_t gen_key, uint64_t ctr0, uint64_t m, uint64_t* keys) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+#pragma unroll 1
+  for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += stride) {
+    const uint64_t y = (ctr0 + 2 * j) * gen_key;
+    const uint64_t z = y + gen_key, z2 = z + gen_key;
+    const uint64_t upper = digits_half(sq64(y, z)), lower = digits_half(sq64(z, z2));
+    keys[j] = (upper << 32) | lower;
+  }
+}
+
 // ============================================================== serving tick
 // Expands the tick's (slot, first, count) entries into batch descriptors
 // and advances each slot's device-side progress counter.
@@ -470,7 +605,7 @@ __global__ __launch_bounds__(256) void k_tick_expand(const sqi::TickHdr* th, con
 namespace sqi {
 
 hipError_t launch_fill(int kind, uint64_t key, uint64_t ctr0, uint64_t n, void* out, const sq_launch_cfg& cfg,
-                       hipStream_t s) {
+                       hipStream_t s, uint64_t step) {
   const int W = kind_bytes(kind), E = 16 / W;
   FillArgs a{};
   a.key = key;
@@ -487,15 +622,43 @@ hipError_t launch_fill(int kind, uint64_t key, uint64_t ctr0, uint64_t n, void* 
   const uint64_t per_chunk = (uint64_t)cfg.block * cfg.unroll;
   a.nchunks = (a.nvec + per_chunk - 1) / per_chunk;
   const bool split = kind == SQ_U32X2 || kind == SQ_F32X2;  // head is even: out is 8-byte aligned
-  a.y_body = (ctr0 + (split ? head / 2 : head)) * key;
-  a.ekey = (uint64_t)(split ? 2 : E) * key;
+  a.step = step;
+  a.dkey = step * key;
+  a.y_body = (ctr0 + (split ? head / 2 : head) * step) * key;
+  a.ekey = (uint64_t)(split ? 2 : E) * a.dkey;
   uint64_t grid = (uint64_t)device_info().cus * cfg.grid_per_cu;
   if (grid > a.nchunks) grid = a.nchunks;
   a.xcd_map = cfg.xcd_map;
   if (a.xcd_map && grid >= 8) grid &= ~7ull;  // XCD-contiguous order needs a multiple of 8
   else a.xcd_map = 0;
   if (grid == 0) grid = 1;                      // the head/tail elements still need a workgroup
-  hipLaunchKernelGGL(fill_kernel(kind, cfg.unroll), dim3((uint32_t)grid), dim3(cfg.block), 0, s, a);
+  const FillKernel k = step == 1 ? fill_kernel<false>(kind, cfg.unroll) : fill_kernel<true>(kind, cfg.unroll);
+  hipLaunchKernelGGL(k, dim3((uint32_t)grid), dim3(cfg.block), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_keys(int kind, uint64_t ctr, const uint64_t* keys, uint64_t m, void* out, const sq_launch_cfg& cfg,
+                       hipStream_t s) {
+  const int W = kind_bytes(kind), E = 16 / W;
+  const bool vec = (((uintptr_t)keys | (uintptr_t)out) & 15) == 0;
+  KeysArgs a{keys, (unsigned char*)out, m, ctr, vec ? m / E : 0};
+  const uint64_t work = vec ? a.nvec : m;
+  uint64_t grid = (uint64_t)device_info().cus * cfg.grid_per_cu;
+  const uint64_t need = (work + cfg.block - 1) / cfg.block;
+  if (grid > need) grid = need;
+  if (grid == 0) grid = 1;  // the tail still needs a workgroup
+  hipLaunchKernelGGL(keys_kernel(kind, vec), dim3((uint32_t)grid), dim3(cfg.block), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_make_keys(uint64_t gen_key, uint64_t ctr0, uint64_t m, uint64_t* keys, const sq_launch_cfg& cfg,
+                            hipStream_t s) {
+  const uint32_t B = 256;
+  uint64_t grid = (uint64_t)device_info().cus * cfg.grid_per_cu;
+  const uint64_t need = (m + B - 1) / B;
+  if (grid > need) grid = need;
+  if (grid == 0) grid = 1;
+  hipLaunchKernelGGL(k_make_keys, dim3((uint32_t)grid), dim3(B), 0, s, gen_key, ctr0, m, keys);
   return hipGetLastError();
 }
 
@@ -513,9 +676,9 @@ static int resident_blocks(const void* k, uint32_t block) {
 }
 
 hipError_t launch_reduce(int kind, uint64_t key, uint64_t ctr0, uint64_t n, sq_sum_result* out, void* ws,
-                         const sq_launch_cfg& cfg, hipStream_t s) {
+                         const sq_launch_cfg& cfg, hipStream_t s, uint64_t step) {
   const uint32_t B = 256;  // reduce workgroups are 256 threads (block_sum128 LDS sized for <= 1024)
-  ReduceKernel k = reduce_kernel(kind, cfg.unroll);
+  ReduceKernel k = step == 1 ? reduce_kernel<false>(kind, cfg.unroll) : reduce_kernel<true>(kind, cfg.unroll);
   const bool split = kind == SQ_U32X2 || kind == SQ_F32X2;
   const uint64_t units = split ? n / 2 : n;  // counters with all their outputs summed
   // Every thread gets the same amount of work, so the grid must be resident
@@ -532,13 +695,16 @@ hipError_t launch_reduce(int kind, uint64_t key, uint64_t ctr0, uint64_t n, sq_s
   a.ctr0 = ctr0;
   a.n = units;
   a.per = units / T + (units % T != 0);
+  a.dkey = step * key;
+  a.y0 = ctr0 * key;
+  a.ythread = a.per * a.dkey;
   a.partials = (uint64_t*)ws;
   hipLaunchKernelGGL(k, dim3((uint32_t)grid), dim3(B), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int scale = (kind == SQ_F32 || kind == SQ_F32X2) ? -24 : (kind == SQ_F64 ? -53 : 0);
   const int split_tail = (split && (n & 1)) ? kind : 0;
-  const uint64_t y_tail = (ctr0 + units) * key;
+  const uint64_t y_tail = (ctr0 + units * step) * key;
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, (const uint64_t*)ws, (uint32_t)grid, n, scale,
                      split_tail, y_tail, key, out);
   return hipGetLastError();

@@ -85,6 +85,14 @@ SIGNATURES = {
     "sq_reduce_workspace_bytes": (ctypes.c_size_t, [_u64]),
     "sq_reduce": (_int, [_int, _u64, _u64, _u64, _vp, _vp, ctypes.c_size_t, _vp]),
     "sq_reduce_cfg": (_int, [_int, _u64, _u64, _u64, _vp, _vp, ctypes.c_size_t, ctypes.POINTER(LaunchCfg), _vp]),
+    "sq_fill_strided": (_int, [_int, _u64, _u64, _u64, _u64, _vp, _vp]),
+    "sq_fill_strided_cfg": (_int, [_int, _u64, _u64, _u64, _u64, _vp, ctypes.POINTER(LaunchCfg), _vp]),
+    "sq_reduce_strided": (_int, [_int, _u64, _u64, _u64, _u64, _vp, _vp, ctypes.c_size_t, _vp]),
+    "sq_reduce_strided_cfg": (_int, [_int, _u64, _u64, _u64, _u64, _vp, _vp, ctypes.c_size_t,
+                                     ctypes.POINTER(LaunchCfg), _vp]),
+    "sq_fill_keys": (_int, [_int, _u64, _vp, _u64, _vp, _vp]),
+    "sq_fill_keys_cfg": (_int, [_int, _u64, _vp, _u64, _vp, ctypes.POINTER(LaunchCfg), _vp]),
+    "sq_make_keys": (_int, [_u64, _u64, _u64, _vp, _vp]),
     "sq_batch_workspace_bytes": (ctypes.c_size_t, [_u32, _u64]),
     "sq_fill_batch": (_int, [_vp, _vp, _vp, _vp, _vp, _u32, _vp, _u64, _vp, ctypes.c_size_t, _vp]),
     "sq_fill_batch_cfg": (_int, [_vp, _vp, _vp, _vp, _vp, _u32, _vp, _u64, _vp, ctypes.c_size_t,
@@ -235,6 +243,50 @@ def uniform_f64(key, ctr0, n, out=None, stream=None):
     return out
 
 
+M64 = (1 << 64) - 1
+
+
+def fill_strided(kind: int, key: int, ctr0: int, step: int, n: int, out=None, stream=None,
+                 launch_cfg: LaunchCfg | None = None):
+    """out[i] = kind's output at counter ctr0 + i*step (split kinds: word i%2 at
+    ctr0 + (i//2)*step)."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty(n, dtype=kind_dtype(kind), device="cuda")
+    args = (kind, key & M64, ctr0 & M64, step & M64, n, _ptr(out))
+    if launch_cfg is None:
+        check(lib().sq_fill_strided(*args, _stream(stream)))
+    else:
+        check(lib().sq_fill_strided_cfg(*args, ctypes.byref(launch_cfg), _stream(stream)))
+    return out
+
+
+def fill_keys(kind: int, ctr: int, keys, out=None, stream=None, launch_cfg: LaunchCfg | None = None, m=None):
+    """Key-counter mode: out[j] = kind's output at counter ctr under keys[j]
+    (keys: a CUDA uint64/int64 tensor, or a device address with m given)."""
+    torch = _torch()
+    if m is None:
+        m = keys.numel()
+    if out is None:
+        out = torch.empty(m, dtype=kind_dtype(kind), device="cuda")
+    args = (kind, ctr & M64, _ptr(keys), m, _ptr(out))
+    if launch_cfg is None:
+        check(lib().sq_fill_keys(*args, _stream(stream)))
+    else:
+        check(lib().sq_fill_keys_cfg(*args, ctypes.byref(launch_cfg), _stream(stream)))
+    return out
+
+
+def make_keys(gen_key: int, ctr0: int, m: int, out=None, stream=None):
+    """m distinct-digit keys generated on the device (key j from squares64 at
+    counters ctr0 + 2j and ctr0 + 2j + 1 under gen_key)."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty(m, dtype=torch.uint64, device="cuda")
+    check(lib().sq_make_keys(gen_key & M64, ctr0 & M64, m, _ptr(out), _stream(stream)))
+    return out
+
+
 # ---------------------------------------------------------------- reduce
 def reduce_workspace(n: int = 0):
     torch = _torch()
@@ -249,6 +301,22 @@ def reduce_async(kind: int, key: int, ctr0: int, n: int, result, ws, stream=None
         check(lib().sq_reduce(*args, _stream(stream)))
     else:
         check(lib().sq_reduce_cfg(*args, ctypes.byref(launch_cfg), _stream(stream)))
+
+
+def reduce_strided_async(kind: int, key: int, ctr0: int, step: int, n: int, result, ws, stream=None,
+                         launch_cfg: LaunchCfg | None = None) -> None:
+    args = (kind, key & M64, ctr0 & M64, step & M64, n, _ptr(result), _ptr(ws), ws.numel() * ws.element_size())
+    if launch_cfg is None:
+        check(lib().sq_reduce_strided(*args, _stream(stream)))
+    else:
+        check(lib().sq_reduce_strided_cfg(*args, ctypes.byref(launch_cfg), _stream(stream)))
+
+
+def reduce_strided(kind: int, key: int, ctr0: int, step: int, n: int, launch_cfg: LaunchCfg | None = None):
+    res = result_tensor()
+    ws = reduce_workspace(n)
+    reduce_strided_async(kind, key, ctr0, step, n, res, ws, launch_cfg=launch_cfg)
+    return read_result(res)
 
 
 def result_tensor():

@@ -98,6 +98,33 @@ def test_reduce_argument_checks():
     assert _rc(L.sq_reduce_cfg, 1, 1, 0, 10, FAKE, FAKE, need, squares.LaunchCfg(256, 3, 8, 0, 16), None)[0] == -1
 
 
+def test_mode_argument_checks():
+    """Strided fill and sum, key-counter mode and key generation reject bad
+    arguments before any device work."""
+    from paper_2004_06278_amd import squares
+
+    L = squares.lib()
+    good_fill = squares.LaunchCfg(256, 8, 16, 0, 16)
+    assert _rc(L.sq_fill_strided_cfg, 9, 1, 0, 3, 10, FAKE, good_fill, None)[0] == -1
+    assert _rc(L.sq_fill_strided_cfg, 4, 1, 0, 3, 10, FAKE + 4, good_fill, None)[0] == -2
+    assert L.sq_fill_strided(0, 1, 0, 3, 0, None, None) == 0
+    need = L.sq_reduce_workspace_bytes(1 << 20)
+    good = squares.LaunchCfg(256, 4, 8, 0, 16)
+    assert _rc(L.sq_reduce_strided_cfg, 7, 1, 0, 3, 10, FAKE, FAKE, need, good, None)[0] == -1
+    assert _rc(L.sq_reduce_strided_cfg, 1, 1, 0, 3, 10, FAKE, FAKE, need - 16, good, None)[0] == -3
+    rc, msg = _rc(L.sq_fill_keys, 4, 0, FAKE, 10, FAKE, None)
+    assert rc == -1 and "key-counter" in msg
+    assert _rc(L.sq_fill_keys, 0, 0, FAKE + 4, 10, FAKE, None)[0] == -2
+    assert _rc(L.sq_fill_keys, 2, 0, FAKE, 10, FAKE + 4, None)[0] == -2
+    assert _rc(L.sq_fill_keys, 0, 0, None, 10, FAKE, None)[0] == -1
+    assert L.sq_fill_keys(0, 0, None, 0, None, None) == 0
+    assert _rc(L.sq_fill_keys_cfg, 0, 0, FAKE, 10, FAKE, squares.LaunchCfg(100, 4, 8, 0, 16), None)[0] == -1
+    assert _rc(L.sq_make_keys, 1, 0, 10, None, None)[0] == -1
+    assert _rc(L.sq_make_keys, 1, 0, 10, FAKE + 4, None)[0] == -2
+    assert _rc(L.sq_make_keys, 1, 0, (1 << 62) + 1, FAKE, None)[0] == -1
+    assert L.sq_make_keys(1, 0, 0, None, None) == 0
+
+
 def test_batch_argument_checks():
     from paper_2004_06278_amd import squares
 
