@@ -138,9 +138,22 @@ def cpu_baseline(key: int, ctr0: int, log2_sample: int = 31) -> dict:
     oracle.exact_sum(oracle.F32, key, ctr0, n, threads=threads)
     oracle.exact_sum(oracle.F64, key, ctr0, n, threads=threads)
     dt = time.perf_counter() - t0
+    # one thread, squares32 only: the figure the paper quotes for one core
+    n1 = 1 << 26
+    t1 = time.perf_counter()
+    oracle.fill_into(oracle.U32, key, ctr0, u32[:n1], threads=1)
+    dt1 = time.perf_counter() - t1
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": round(4 * n / dt / 1e9, 3), "unit": "Gnum/s", "cores": threads, "kind": "oracle",
             "sample": f"2^{log2_sample} counters of each of the 4 step operations (same key and ctr0; fills "
-                      f"into a reused 2^26-element host buffer), {threads} host threads, {dt:.2f} s wall"}
+                      f"into a reused 2^26-element host buffer), {threads} host threads, {dt:.2f} s wall",
+            "one_thread_sq32_gnum_s": round(n1 / dt1 / 1e9, 3), "host_cpu": model,
+            "host_cpus_visible": os.cpu_count()}
 
 
 def batch_speedup(sq, torch) -> dict:

@@ -4,7 +4,7 @@ Runs the tuner for fill, reduce and batch on the current GPU and writes the
 table as JSON.  The library loads `tune_gfx950.json` next to it at start-up
 (or the file named by $SQ_TUNE_CACHE).
 
-    python -m paper_2004_06278_amd.autotune [--out PATH] [--max-gib 16]
+    python -m paper_2004_06278_amd.autotune [--out PATH] [--max-gib 64]
 """
 from __future__ import annotations
 
@@ -20,7 +20,7 @@ def main() -> int:
 
     p = argparse.ArgumentParser()
     p.add_argument("--out", default=sq.TUNE_TABLE)
-    p.add_argument("--max-gib", type=int, default=16)
+    p.add_argument("--max-gib", type=int, default=64)
     p.add_argument("--ops", type=int, default=7, help="bit mask: 1 fill, 2 reduce, 4 batch")
     a = p.parse_args()
     import torch

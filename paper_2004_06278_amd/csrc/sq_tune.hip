@@ -59,7 +59,10 @@ bool cfg_valid(sq_op op, const sq_launch_cfg& c) {
 sq_launch_cfg default_cfg(sq_op op, int kind, uint64_t n) {
   (void)n;
   switch (op) {
-    case SQ_OP_FILL: return sq_launch_cfg{256, 8, 32, 1, 16};
+    // 1024 threads x 8 vectors: each workgroup step writes 128 KiB
+    // contiguous, the shape that reached the HBM store ceiling in a
+    // store-only kernel on MI355X
+    case SQ_OP_FILL: return sq_launch_cfg{1024, 8, 16, 0, 16};
     case SQ_OP_REDUCE: return sq_launch_cfg{256, 4, 8, 0, 16};
     default: return sq_launch_cfg{512, 1, 4, 0, 16};
   }
@@ -148,23 +151,36 @@ static hipError_t same_bytes(Scratch& S, uint64_t bytes, bool* same) {
   return e;
 }
 
-template <typename F>
-static hipError_t time_best(Scratch& S, F launch, int reps, float* best_ms) {
-  hipError_t e = launch();  // warm-up
+// Times the incumbent and a candidate in alternation (reps pairs after one
+// warm-up of each), so clock and thermal drift during tuning affect both
+// alike; returns the median of each.
+template <typename FA, typename FB>
+static hipError_t time_pair(Scratch& S, FA inc, FB cand, int reps, float* ms_inc, float* ms_cand) {
+  hipError_t e = inc();
+  if (e == hipSuccess) e = cand();
   if (e != hipSuccess) return e;
-  float best = 1e30f;
+  std::vector<float> a, b;
   for (int r = 0; r < reps; ++r) {
-    if ((e = hipEventRecord(S.e0, S.s)) != hipSuccess) return e;
-    if ((e = launch()) != hipSuccess) return e;
-    if ((e = hipEventRecord(S.e1, S.s)) != hipSuccess) return e;
-    if ((e = hipEventSynchronize(S.e1)) != hipSuccess) return e;
-    float ms = 0;
-    if ((e = hipEventElapsedTime(&ms, S.e0, S.e1)) != hipSuccess) return e;
-    best = std::min(best, ms);
+    for (int which = 0; which < 2; ++which) {
+      if ((e = hipEventRecord(S.e0, S.s)) != hipSuccess) return e;
+      if ((e = which == 0 ? inc() : cand()) != hipSuccess) return e;
+      if ((e = hipEventRecord(S.e1, S.s)) != hipSuccess) return e;
+      if ((e = hipEventSynchronize(S.e1)) != hipSuccess) return e;
+      float ms = 0;
+      if ((e = hipEventElapsedTime(&ms, S.e0, S.e1)) != hipSuccess) return e;
+      (which == 0 ? a : b).push_back(ms);
+    }
   }
-  *best_ms = best;
+  std::sort(a.begin(), a.end());
+  std::sort(b.begin(), b.end());
+  *ms_inc = a[a.size() / 2];
+  *ms_cand = b[b.size() / 2];
   return hipSuccess;
 }
+
+// Representative problem size of a size bucket: the middle of the bucket,
+// and 2^32 outputs for the open-ended last one.
+static uint64_t bucket_size(int b) { return b == kBuckets - 1 ? (1ull << 32) : (1ull << (4 * b + 14)); }
 
 static bool verbose() {
   static const bool v = [] {
@@ -262,33 +278,33 @@ int sq_autotune(uint32_t op_mask, uint64_t max_bytes, const char* save_path) {
     for (int kind = 0; kind < kKinds; ++kind) {
       const uint64_t W = kind_bytes(kind);
       for (int b = 0; b < kBuckets; ++b) {
-        uint64_t n = std::min<uint64_t>(1ull << (4 * b + 15), half / W);
+        uint64_t n = std::min<uint64_t>(bucket_size(b), half / W);
         n -= 3;  // ragged: exercises the tail (the buffers are aligned, as for timing)
         const sq_launch_cfg ref = default_cfg(SQ_OP_FILL, kind, n);
         if ((e = launch_fill(kind, key, ctr0, n, (unsigned char*)S.b, ref, S.s)) != hipSuccess) break;
         std::swap(S.a, S.b);  // reference now in a
-        // the default is the incumbent; a candidate must beat it by 2% (timing noise)
-        float best = 1e30f;
+        // The default is the first incumbent.  Each candidate is timed in
+        // alternation with the incumbent and replaces it when its median is
+        // 2% lower (below timing noise) and its bytes equal the reference's.
         sq_launch_cfg best_c = ref;
-        e = time_best(S, [&] { return launch_fill(kind, key, ctr0, n, (unsigned char*)S.b, ref, S.s); }, 5,
-                      &best);
-        if (e != hipSuccess) break;
-        report("fill-default", kind, b, n, ref, best, true);
         for (uint32_t blk : {256u, 512u, 1024u})
           for (uint32_t u : {4u, 8u})
-            for (uint32_t g : {4u, 8u, 16u, 32u})
+            for (uint32_t g : {1u, 2u, 4u, 8u, 16u, 32u, 64u})
               for (uint32_t x : {0u, 1u}) {
-                sq_launch_cfg c{blk, u, g, x, 16};
-                float ms = 0;
-                e = time_best(S, [&] { return launch_fill(kind, key, ctr0, n, (unsigned char*)S.b, c, S.s); },
-                              5, &ms);
+                const sq_launch_cfg c{blk, u, g, x, 16};
+                float ms_inc = 0, ms = 0;
+                const sq_launch_cfg inc = best_c;
+                e = time_pair(
+                    S, [&] { return launch_fill(kind, key, ctr0, n, (unsigned char*)S.b, inc, S.s); },
+                    [&] { return launch_fill(kind, key, ctr0, n, (unsigned char*)S.b, c, S.s); }, 5, &ms_inc, &ms);
                 if (e != hipSuccess) break;
                 bool same = false;
                 if ((e = same_bytes(S, n * W, &same)) != hipSuccess) break;
                 report("fill", kind, b, n, c, ms, same);
-                if (same && ms < 0.98f * best) { best = ms; best_c = c; }
+                if (same && ms < 0.98f * ms_inc) best_c = c;
               }
         if (e != hipSuccess) break;
+        report("fill-chosen", kind, b, n, best_c, 0.f, true);
         set_entry(SQ_OP_FILL, kind, b, best_c);
       }
       if (e != hipSuccess) break;
@@ -302,18 +318,18 @@ int sq_autotune(uint32_t op_mask, uint64_t max_bytes, const char* save_path) {
     void* ws = (unsigned char*)S.b + 4096;
     for (int kind = 0; kind < kKinds && e == hipSuccess; ++kind) {
       for (int b = 0; b < kBuckets && e == hipSuccess; ++b) {
-        const uint64_t n = (1ull << (4 * b + 15)) - 5;
+        const uint64_t n = bucket_size(b) - 5;
         const sq_launch_cfg ref = default_cfg(SQ_OP_REDUCE, kind, n);
-        float best = 1e30f;
+        if ((e = launch_reduce(kind, key, ctr0, n, res, ws, ref, S.s)) != hipSuccess) break;
         sq_launch_cfg best_c = ref;
-        e = time_best(S, [&] { return launch_reduce(kind, key, ctr0, n, res, ws, ref, S.s); }, 5, &best);
-        if (e != hipSuccess) break;
-        report("reduce-default", kind, b, n, ref, best, true);
         for (uint32_t u : {1u, 2u, 4u})
           for (uint32_t g : {2u, 4u, 8u, 16u, 32u}) {
-            sq_launch_cfg c{256, u, g, 0, 16};
-            float ms = 0;
-            e = time_best(S, [&] { return launch_reduce(kind, key, ctr0, n, cand, ws, c, S.s); }, 5, &ms);
+            const sq_launch_cfg c{256, u, g, 0, 16};
+            const sq_launch_cfg inc = best_c;
+            float ms_inc = 0, ms = 0;
+            e = time_pair(
+                S, [&] { return launch_reduce(kind, key, ctr0, n, cand, ws, inc, S.s); },
+                [&] { return launch_reduce(kind, key, ctr0, n, cand, ws, c, S.s); }, 5, &ms_inc, &ms);
             if (e != hipSuccess) break;
             sq_sum_result h[2];
             if ((e = hipMemcpyAsync(&h[0], res, sizeof h[0], hipMemcpyDeviceToHost, S.s)) != hipSuccess) break;
@@ -321,9 +337,12 @@ int sq_autotune(uint32_t op_mask, uint64_t max_bytes, const char* save_path) {
             if ((e = hipStreamSynchronize(S.s)) != hipSuccess) break;
             const bool same = std::memcmp(&h[0], &h[1], sizeof h[0]) == 0;
             report("reduce", kind, b, n, c, ms, same);
-            if (same && ms < 0.98f * best) { best = ms; best_c = c; }
+            if (same && ms < 0.98f * ms_inc) best_c = c;
           }
-        if (e == hipSuccess) set_entry(SQ_OP_REDUCE, kind, b, best_c);
+        if (e == hipSuccess) {
+          report("reduce-chosen", kind, b, n, best_c, 0.f, true);
+          set_entry(SQ_OP_REDUCE, kind, b, best_c);
+        }
       }
     }
     if (e != hipSuccess) return fail_hip(e, "autotune reduce");
@@ -375,29 +394,30 @@ int sq_autotune(uint32_t op_mask, uint64_t max_bytes, const char* save_path) {
       if (e == hipSuccess) e = hipMemsetAsync(S.a, 0, used, S.s);
       if (e == hipSuccess) e = hipMemsetAsync(S.b, 0, used, S.s);
       const sq_launch_cfg ref = default_cfg(SQ_OP_BATCH, 0, 0);
-      float best = 1e30f;
       sq_launch_cfg best_c = ref;
       if (e == hipSuccess) {
         BatchDesc d{dk, dc, dl, dof, dkd, m, (unsigned char*)S.a, budget};
-        e = time_best(S, [&] { return launch_batch(d, ws, ref, S.s); }, 5, &best);
-        report("batch-default", -1, b, pos, ref, best, true);
+        e = launch_batch(d, ws, ref, S.s);
       }
       for (uint32_t tl : {14u, 16u, 18u, 20u}) {
         for (uint32_t blk : {256u, 512u, 1024u}) {
           for (uint32_t g : {2u, 4u, 8u, 16u}) {
             if (e != hipSuccess) break;
-            sq_launch_cfg c{blk, 1, g, 0, tl};
+            const sq_launch_cfg c{blk, 1, g, 0, tl};
+            const sq_launch_cfg inc = best_c;
             BatchDesc d{dk, dc, dl, dof, dkd, m, (unsigned char*)S.b, budget};
-            float ms = 0;
-            e = time_best(S, [&] { return launch_batch(d, ws, c, S.s); }, 5, &ms);
+            float ms_inc = 0, ms = 0;
+            e = time_pair(S, [&] { return launch_batch(d, ws, inc, S.s); },
+                          [&] { return launch_batch(d, ws, c, S.s); }, 5, &ms_inc, &ms);
             if (e != hipSuccess) break;
             bool same = false;
             if ((e = same_bytes(S, used, &same)) != hipSuccess) break;
             report("batch", -1, b, pos, c, ms, same);
-            if (same && ms < 0.98f * best) { best = ms; best_c = c; }
+            if (same && ms < 0.98f * ms_inc) best_c = c;
           }
         }
       }
+      if (e == hipSuccess) report("batch-chosen", -1, b, pos, best_c, 0.f, true);
       hipError_t fe = hipFree(desc);
       if (e == hipSuccess) e = fe;
       if (e == hipSuccess) {
