@@ -79,10 +79,12 @@ def lib() -> ctypes.CDLL:
             L.oracle_fill_strided.restype = ctypes.c_int
             L.oracle_fill_keys.argtypes = [ctypes.c_int, u64, vp, u64, vp]
             L.oracle_fill_keys.restype = ctypes.c_int
-            L.oracle_key_index.argtypes = [u64]
+            L.oracle_key_index.argtypes = [u64, u64]
             L.oracle_key_index.restype = u64
-            L.oracle_key_half.argtypes = [u64]
-            L.oracle_key_half.restype = ctypes.c_uint32
+            L.oracle_key_upper.argtypes = [u64]
+            L.oracle_key_upper.restype = ctypes.c_uint32
+            L.oracle_key_lower.argtypes = [u64]
+            L.oracle_key_lower.restype = ctypes.c_uint32
             L.oracle_make_keys.argtypes = [u64, u64, u64, vp]
             L.oracle_make_keys.restype = ctypes.c_int
             _lib = L
@@ -171,15 +173,20 @@ def fill_keys(kind: int, ctr: int, keys) -> np.ndarray:
     return out
 
 
-KEY_CHOICES = 16 * 15 * 14 * 13 * 12 * 11 * 10 * 9
+KEY_CHOICES_HI = 16 * 15 * 14 * 13 * 12 * 11 * 10 * 9
+KEY_CHOICES_LO = 8 * 15 * 14 * 13 * 12 * 11 * 10 * 9
 
 
-def key_index(r: int) -> int:
-    return int(lib().oracle_key_index(r & (2**64 - 1)))
+def key_index(r: int, choices: int) -> int:
+    return int(lib().oracle_key_index(r & (2**64 - 1), choices))
 
 
-def key_half(u: int) -> int:
-    return int(lib().oracle_key_half(u))
+def key_upper(u: int) -> int:
+    return int(lib().oracle_key_upper(u))
+
+
+def key_lower(u: int) -> int:
+    return int(lib().oracle_key_lower(u))
 
 
 def make_keys(gen_key: int, ctr0: int, m: int) -> np.ndarray:

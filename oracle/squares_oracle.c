@@ -265,28 +265,43 @@ int oracle_fill_keys(int kind, uint64_t ctr, const uint64_t *keys, uint64_t m, u
 /* ------------------------------------------------------------------------
  * Distinct-digit keys (Section 3, Discussion): the upper 8 hex digits of a key
  * are mutually different, so are the lower 8, and the digits are random.
- * The paper gives the property, not a procedure; the procedure used here is
- * this library's own, with squares64 as the random source so that key j is a
- * function of (gen_key, ctr0, j) alone:
- *   half h of key j (h = 0 upper, 1 lower) draws r = squares64(ctr0 + 2j + h,
- *   gen_key), maps it to u = floor(r * N / 2^64) with N = 16*15*...*9 (the
- *   number of ordered choices of 8 digits out of 16), and decodes u as the
- *   choices of a Fisher-Yates shuffle of the digits 0..15 stopped after 8
- *   steps: step i (radix 16 - i) takes the digit at position i + (u mod
- *   radix) of the partly shuffled list and u becomes u div radix.  The first
- *   digit taken is the half's most significant hex digit.
+ * Reading adopted where the paper is silent: the least significant hex digit
+ * is odd, so that ctr -> ctr*key is a bijection mod 2^64 (the Weyl sequence
+ * behind the uniformity argument of Section 2 visits every residue only with
+ * an odd increment).  The paper gives the property, not a procedure; the
+ * procedure here is this library's own, with squares64 as the random source
+ * so that key j is a function of (gen_key, ctr0, j) alone:
+ *   the upper half of key j draws r = squares64(ctr0 + 2j, gen_key), maps it
+ *   to u = floor(r * N_HI / 2^64) with N_HI = 16*15*...*9 (ordered choices of
+ *   8 digits out of 16) and decodes u as the choices of a Fisher-Yates
+ *   shuffle of the digits 0..15 stopped after 8 steps: step i (radix 16 - i)
+ *   takes the digit at position i + (u mod radix) of the partly shuffled list
+ *   and u becomes u div radix; the first digit taken is the most significant.
+ *   The lower half draws r = squares64(ctr0 + 2j + 1, gen_key) and
+ *   u = floor(r * N_LO / 2^64) with N_LO = 8 * 15*14*...*9; its least
+ *   significant digit is the odd digit 2*(u mod 8) + 1 (u becomes u div 8),
+ *   which is moved to the front of the list; steps i = 1..7 then take the
+ *   other seven digits as above, most significant first.
  * ------------------------------------------------------------------------ */
-#define ORACLE_KEY_CHOICES 518918400ull /* 16*15*14*13*12*11*10*9 */
+#define ORACLE_KEY_CHOICES_HI 518918400ull /* 16*15*14*13*12*11*10*9 */
+#define ORACLE_KEY_CHOICES_LO 259459200ull /* 8 * 15*14*13*12*11*10*9 */
 
-/* floor(r * N / 2^64), with the 128-bit product formed exactly. */
-uint64_t oracle_key_index(uint64_t r)
+/* floor(r * choices / 2^64), with the 128-bit product formed exactly. */
+uint64_t oracle_key_index(uint64_t r, uint64_t choices)
 {
-    unsigned __int128 p = (unsigned __int128)r * ORACLE_KEY_CHOICES;
+    unsigned __int128 p = (unsigned __int128)r * choices;
     return (uint64_t)(p >> 64);
 }
 
-/* The 8 hex digits (as a 32-bit half key) that index u < N selects. */
-uint32_t oracle_key_half(uint64_t u)
+static void swap_digits(int *digits, int a, int b)
+{
+    int t = digits[a];
+    digits[a] = digits[b];
+    digits[b] = t;
+}
+
+/* The 8 hex digits (a 32-bit half key) that index u < N_HI selects. */
+uint32_t oracle_key_upper(uint64_t u)
 {
     int digits[16];
     for (int i = 0; i < 16; ++i) digits[i] = i;
@@ -295,19 +310,38 @@ uint32_t oracle_key_half(uint64_t u)
         int radix = 16 - i;
         int pick = i + (int)(u % (uint64_t)radix);
         u /= (uint64_t)radix;
-        int d = digits[pick];
-        digits[pick] = digits[i];
-        digits[i] = d;
-        half = (half << 4) | (uint32_t)d;
+        swap_digits(digits, i, pick);
+        half = (half << 4) | (uint32_t)digits[i];
     }
     return half;
+}
+
+/* The lower half that index u < N_LO selects: odd last digit first. */
+uint32_t oracle_key_lower(uint64_t u)
+{
+    int digits[16];
+    for (int i = 0; i < 16; ++i) digits[i] = i;
+    int odd = 2 * (int)(u % 8) + 1;
+    u /= 8;
+    swap_digits(digits, 0, odd);
+    uint32_t half = 0;
+    for (int i = 1; i < 8; ++i) {
+        int radix = 16 - i;
+        int pick = i + (int)(u % (uint64_t)radix);
+        u /= (uint64_t)radix;
+        swap_digits(digits, i, pick);
+        half = (half << 4) | (uint32_t)digits[i];
+    }
+    return (half << 4) | (uint32_t)odd;
 }
 
 int oracle_make_keys(uint64_t gen_key, uint64_t ctr0, uint64_t m, uint64_t *keys)
 {
     for (uint64_t j = 0; j < m; ++j) {
-        uint64_t upper = oracle_key_half(oracle_key_index(oracle_squares64(ctr0 + 2 * j, gen_key)));
-        uint64_t lower = oracle_key_half(oracle_key_index(oracle_squares64(ctr0 + 2 * j + 1, gen_key)));
+        uint64_t r_hi = oracle_squares64(ctr0 + 2 * j, gen_key);
+        uint64_t r_lo = oracle_squares64(ctr0 + 2 * j + 1, gen_key);
+        uint64_t upper = oracle_key_upper(oracle_key_index(r_hi, ORACLE_KEY_CHOICES_HI));
+        uint64_t lower = oracle_key_lower(oracle_key_index(r_lo, ORACLE_KEY_CHOICES_LO));
         keys[j] = (upper << 32) | lower;
     }
     return 0;

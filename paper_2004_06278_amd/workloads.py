@@ -7,7 +7,9 @@ one module both sides receive their inputs from.
 
 Keys follow the paper's advice (Section 3, Discussion): an irregular bit
 pattern whose upper 8 hex digits are mutually different and whose lower 8
-hex digits are mutually different, the digits chosen at random.
+hex digits are mutually different, the digits chosen at random.  The least
+significant digit is drawn first from the odd digits (a reading where the
+paper is silent: an odd key makes ctr -> ctr*key a bijection mod 2^64).
 """
 from __future__ import annotations
 
@@ -31,12 +33,14 @@ def rng(seed: int) -> np.random.Generator:
 
 
 def distinct_digit_key(g: np.random.Generator) -> int:
-    """One key: each 8-digit half is 8 different hex digits in random order."""
-    hi = g.permutation(16)[:8]
-    lo = g.permutation(16)[:8]
+    """One key: each 8-digit half is 8 different hex digits in random order,
+    the last digit odd."""
+    hi = [int(d) for d in g.permutation(16)[:8]]
+    odd = 2 * int(g.integers(0, 8)) + 1
+    lo = [int(d) for d in g.permutation(16) if d != odd][:7] + [odd]
     key = 0
-    for d in list(hi) + list(lo):
-        key = (key << 4) | int(d)
+    for d in hi + lo:
+        key = (key << 4) | d
     return key
 
 

@@ -453,10 +453,11 @@ def _hex_digits(half: int) -> list[int]:
     return [(half >> (28 - 4 * i)) & 15 for i in range(8)]
 
 
-def _index_of_half(half: int) -> int:
-    """Inverse of the decode, written from the shuffle's definition in the other
-    direction: replay the partial Fisher-Yates shuffle and read each step's
-    choice (position in the remaining list) as a mixed-radix digit."""
+def _index_of_upper(half: int) -> int:
+    """Inverse of the upper-half decode, written from the shuffle's definition
+    in the other direction: replay the partial Fisher-Yates shuffle and read
+    each step's choice (position in the remaining list) as a mixed-radix
+    digit."""
     pool = list(range(16))
     u, scale = 0, 1
     for i, d in enumerate(_hex_digits(half)):
@@ -468,68 +469,112 @@ def _index_of_half(half: int) -> int:
     return u
 
 
+def _index_of_lower(half: int) -> int:
+    """Inverse of the lower-half decode: the odd last digit is the first,
+    radix-8 choice; the other seven digits are the shuffle's steps 1..7."""
+    digits = _hex_digits(half)
+    odd = digits[7]
+    assert odd % 2 == 1
+    pool = list(range(16))
+    pool[0], pool[odd] = pool[odd], pool[0]
+    u, scale = (odd - 1) // 2, 8
+    for i, d in enumerate(digits[:7], start=1):
+        q = pool.index(d)
+        assert q >= i
+        u += (q - i) * scale
+        scale *= 16 - i
+        pool[q], pool[i] = pool[i], pool[q]
+    return u
+
+
 def test_key_half_hand_values(oracle_mod):
-    """Worked by hand: index 0 takes digits in order; index 1 first takes
-    digit 1 (then 0, which the swap moved to position 1); the last index takes
-    the last remaining digit at every step: 15, then 0 (moved to position 15
-    by the first swap), then 1, 2, ..."""
+    """Worked by hand.  Upper half: index 0 takes the digits in order; index 1
+    first takes digit 1 (then 0, which the swap moved to position 1); the last
+    index takes the last remaining digit at every step: 15, then 0 (moved to
+    position 15 by the first swap), then 1, 2, ...  Lower half: index 0 puts
+    odd digit 1 last and takes 0, 2, 3, ... in front; index 1 chooses odd
+    digit 3; the last index chooses 15 and then the last remaining digit at
+    every step: 0 (moved to position 15), 1, 2, ..."""
     o = oracle_mod
-    assert o.KEY_CHOICES == 518918400
-    assert o.key_half(0) == 0x01234567
-    assert o.key_half(1) == 0x10234567
-    assert o.key_half(16) == 0x02134567  # second step's choice 1: position 2 after the first step
-    assert o.key_half(o.KEY_CHOICES - 1) == 0xF0123456
+    assert o.KEY_CHOICES_HI == 518918400 and o.KEY_CHOICES_LO == 259459200
+    assert o.key_upper(0) == 0x01234567
+    assert o.key_upper(1) == 0x10234567
+    assert o.key_upper(16) == 0x02134567  # second step's choice 1: position 2 after the first step
+    assert o.key_upper(o.KEY_CHOICES_HI - 1) == 0xF0123456
+    assert o.key_lower(0) == 0x02345671
+    assert o.key_lower(1) == 0x12045673   # odd digit 3 swapped with 0: list 3,1,2,0,4,..., then 1,2,0,4,5,6,7
+    assert o.key_lower(8) == 0x20345671   # first shuffle step's choice 1
+    assert o.key_lower(o.KEY_CHOICES_LO - 1) == 0x0123456F
 
 
 def test_key_half_is_a_bijection_sample(oracle_mod):
     """Decoding then re-encoding returns the index (so distinct indices give
-    distinct halves), and every half has 8 different digits."""
+    distinct halves); every half has 8 different digits and every lower half
+    ends in an odd digit."""
     o = oracle_mod
     g = np.random.Generator(np.random.PCG64(41))
-    us = [0, 1, 15, 16, 239, 240, o.KEY_CHOICES - 1] + [int(v) for v in g.integers(0, o.KEY_CHOICES, 3000)]
-    for u in us:
-        h = o.key_half(u)
-        assert len(set(_hex_digits(h))) == 8
-        assert _index_of_half(h) == u
+    for N, dec, enc in ((o.KEY_CHOICES_HI, o.key_upper, _index_of_upper),
+                        (o.KEY_CHOICES_LO, o.key_lower, _index_of_lower)):
+        us = [0, 1, 7, 8, 15, 16, 239, 240, N - 1] + [int(v) for v in g.integers(0, N, 3000)]
+        for u in us:
+            h = dec(u)
+            assert len(set(_hex_digits(h))) == 8
+            assert enc(h) == u
+            if dec is o.key_lower:
+                assert h & 1
 
 
 def test_key_index_end_points(oracle_mod):
     o = oracle_mod
-    N = o.KEY_CHOICES
-    assert o.key_index(0) == 0
-    assert o.key_index(2**64 - 1) == N - 1
-    assert o.key_index(2**63) == N // 2
-    g = np.random.Generator(np.random.PCG64(43))
-    for r in g.integers(0, 2**64, size=200, dtype=np.uint64):
-        assert o.key_index(int(r)) == (int(r) * N) >> 64
+    for N in (o.KEY_CHOICES_HI, o.KEY_CHOICES_LO):
+        assert o.key_index(0, N) == 0
+        assert o.key_index(2**64 - 1, N) == N - 1
+        assert o.key_index(2**63, N) == N // 2
+        g = np.random.Generator(np.random.PCG64(43))
+        for r in g.integers(0, 2**64, size=200, dtype=np.uint64):
+            assert o.key_index(int(r), N) == (int(r) * N) >> 64
 
 
 def test_make_keys_property_and_source(oracle_mod):
-    """Each key has distinct-digit halves (Section 3, Discussion) and its halves
-    come from squares64 at counters ctr0 + 2j and ctr0 + 2j + 1; counters wrap."""
+    """Each key has distinct-digit halves (Section 3, Discussion) and an odd
+    last digit; its halves come from squares64 at counters ctr0 + 2j and
+    ctr0 + 2j + 1; counters wrap."""
     o = oracle_mod
     gk, c0 = 0x9E3779B97F4A7C15, 2**64 - 7
     keys = o.make_keys(gk, c0, 64)
     for j, k in enumerate(int(v) for v in keys):
         up, lo = k >> 32, k & 0xFFFFFFFF
-        assert len(set(_hex_digits(up))) == 8 and len(set(_hex_digits(lo))) == 8
+        assert len(set(_hex_digits(up))) == 8 and len(set(_hex_digits(lo))) == 8 and k & 1
         r_up = o.squares64((c0 + 2 * j) % 2**64, gk)
         r_lo = o.squares64((c0 + 2 * j + 1) % 2**64, gk)
-        assert _index_of_half(up) == (r_up * o.KEY_CHOICES) >> 64
-        assert _index_of_half(lo) == (r_lo * o.KEY_CHOICES) >> 64
+        assert _index_of_upper(up) == (r_up * o.KEY_CHOICES_HI) >> 64
+        assert _index_of_lower(lo) == (r_lo * o.KEY_CHOICES_LO) >> 64
     # a later window of the same range is the same keys
     assert o.make_keys(gk, (c0 + 10) % 2**64, 5).tolist() == keys[5:10].tolist()
 
 
 def test_make_keys_digit_frequencies(oracle_mod):
-    """Every digit shows up at every position with frequency near 1/16 (loose
-    chi-square screen over 40000 keys), and no two keys collide."""
+    """Digit frequencies per position match the procedure's exact
+    distribution (loose chi-square screens over 40000 keys): 1/16 each in the
+    upper half; 1/8 for each odd digit in the last position; in the other
+    lower positions 1/15 for an even digit and 7/120 for an odd one (the odd
+    last digit is drawn first and excluded).  No two keys collide."""
     o = oracle_mod
     keys = o.make_keys(0x7C2B5E19A4D3F680, 0, 40000)
     assert np.unique(keys).size == keys.size
+    odd = np.arange(16) % 2 == 1
     for pos in range(16):
         d = ((keys >> np.uint64(60 - 4 * pos)) & np.uint64(15)).astype(np.int64)
-        cnt = np.bincount(d, minlength=16)
-        exp = keys.size / 16
-        chi2 = float(((cnt - exp) ** 2 / exp).sum())
-        assert chi2 < 60, (pos, chi2)  # 15 dof: p ~ 1e-7
+        cnt = np.bincount(d, minlength=16).astype(float)
+        if pos < 8:
+            p = np.full(16, 1 / 16)
+        elif pos == 15:
+            p = np.where(odd, 1 / 8, 0.0)
+            assert cnt[~odd].sum() == 0
+        else:
+            p = np.where(odd, 7 / 120, 1 / 15)
+        assert abs(p.sum() - 1) < 1e-12
+        m = p > 0
+        exp = keys.size * p[m]
+        chi2 = float(((cnt[m] - exp) ** 2 / exp).sum())
+        assert chi2 < 60, (pos, chi2)  # at most 15 dof: p ~ 1e-7
