@@ -76,6 +76,22 @@ int sq_version(void);
 int sq_init(void);
 
 /* ------------------------------------------------------------------------
+ * Scalar evaluation in the paper's argument order (ctr, key): squares32
+ * (Section 2) and squares64 (Section 5) at one counter, computed by a
+ * one-thread kernel on the current device (null stream) and copied back.
+ * Synchronous; for spot checks and tests, not for throughput.  `value` is a
+ * HOST pointer (null: SQ_EINVAL).  The library keeps one 256-byte device
+ * buffer per device for these calls (allocated on first use).
+ * ------------------------------------------------------------------------ */
+int sq32_at(uint64_t ctr, uint64_t key, uint32_t *value);
+int sq64_at(uint64_t ctr, uint64_t key, uint64_t *value);
+
+/* Host helper: the 128-bit integer (hi:lo) times 2^pow2_exp rounded to the
+ * nearest double, ties to even -- the rounding sq_reduce applies to its
+ * exact sum (scale -24 for F32/F32X2, -53 for F64, 0 for integer kinds). */
+double sq_u128_to_double_scaled(uint64_t lo, uint64_t hi, int pow2_exp);
+
+/* ------------------------------------------------------------------------
  * Bulk fills over a counter range (Section 2 squares32, Section 5 squares64).
  *   out[i] = f(ctr0 + i mod 2^64, key),  i in [0, n)
  * `out` must be aligned to 4 bytes (U32, F32) or 8 bytes (other kinds), else
@@ -200,17 +216,22 @@ int sq_fill_keys_cfg(sq_kind kind, uint64_t ctr, const uint64_t *keys, uint64_t 
 /* ------------------------------------------------------------------------
  * Distinct-digit keys on the device (Section 3, Discussion: a key's upper 8
  * hex digits are mutually different, so are its lower 8, and the digits
- * are random).  Key j depends only on (gen_key, ctr0, j):
- *   half h (0: upper 32 bits, 1: lower) takes r = squares64(ctr0 + 2j + h,
- *   gen_key) mod 2^64 counters, u = floor(r * N / 2^64) with
- *   N = 16*15*...*9 = 518918400, and the digits of a partial Fisher-Yates
- *   shuffle of 0..15 whose step i (i = 0..7) takes the digit at position
- *   i + (u mod (16 - i)) and then sets u = u div (16 - i); the first digit
- *   taken is the most significant.
- * So keys[ctr0 .. ] windows compose: sq_make_keys(g, c + 2k, ...) yields keys
- * k, k+1, ... of sq_make_keys(g, c, ...).  `keys` is a device array of m
- * uint64 (8-byte aligned); m <= 2^62.  gen_key should itself be a
- * distinct-digit key.
+ * are random); the least significant digit is odd, so ctr -> ctr*key is a
+ * bijection mod 2^64.  Key j depends only on (gen_key, ctr0, j):
+ *   upper 32 bits: r = squares64(ctr0 + 2j, gen_key), u = floor(r * N / 2^64)
+ *   with N = 16*15*...*9 = 518918400, and the digits of a partial
+ *   Fisher-Yates shuffle of 0..15 whose step i (i = 0..7) takes the digit at
+ *   position i + (u mod (16 - i)) and then sets u = u div (16 - i); the first
+ *   digit taken is the most significant.
+ *   lower 32 bits: r = squares64(ctr0 + 2j + 1, gen_key),
+ *   u = floor(r * 8 * 15*14*...*9 / 2^64); the last digit is the odd digit
+ *   2 * (u mod 8) + 1 (then u = u div 8), moved to position 0 of the list;
+ *   steps i = 1..7 as above give the other seven digits, most significant
+ *   first.
+ * (counters mod 2^64).  So windows compose: sq_make_keys(g, c + 2k, ...)
+ * yields keys k, k+1, ... of sq_make_keys(g, c, ...).  `keys` is a device
+ * array of m uint64 (8-byte aligned, else SQ_EALIGN); m <= 2^62, else
+ * SQ_EINVAL.  gen_key should itself be a distinct-digit key.
  * ------------------------------------------------------------------------ */
 int sq_make_keys(uint64_t gen_key, uint64_t ctr0, uint64_t m, uint64_t *keys, void *stream);
 
@@ -220,9 +241,13 @@ int sq_make_keys(uint64_t gen_key, uint64_t ctr0, uint64_t m, uint64_t *keys, vo
  * ctr0s[s] under keys[s] at byte offset offs[s] of the arena `out` of
  * `out_bytes` bytes.  All five descriptor arrays are DEVICE arrays of m
  * entries; offs[s] must be a multiple of the element size, streams must not
- * overlap.  The kernels check every descriptor on the device: a stream with
- * an unknown kind, a misaligned offset or a range past out_bytes is skipped
- * (nothing written) and counted; sq_batch_errors() reads that count.
+ * overlap (not checked unless $SQ_DEBUG_VALIDATE is set: then the call copies
+ * the descriptors to the host, synchronising the stream, and returns
+ * SQ_EINVAL / SQ_EALIGN for a stream the kernels would skip or for
+ * overlapping ranges).  The kernels check every descriptor on the device:
+ * a stream with an unknown kind, a misaligned offset or a range past
+ * out_bytes is skipped (nothing written) and counted; sq_batch_errors()
+ * reads that count.
  * `ws` needs sq_batch_workspace_bytes(m, out_bytes) bytes (16-byte aligned):
  * a header, the tile scan and a tile-to-stream map sized for the arena.
  * The work is split into tiles of 2^tile_log2 outputs; a tile scan and one

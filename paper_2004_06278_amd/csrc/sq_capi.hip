@@ -4,11 +4,13 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <mutex>
 #include <string>
 #include <unordered_map>
+#include <vector>
 
 #include "sq_internal.hpp"
 
@@ -124,6 +126,43 @@ int sq64x2_fill(uint64_t key, uint64_t ctr0, uint64_t n, uint32_t* out, void* st
 int sq_uniform_f32x2(uint64_t key, uint64_t ctr0, uint64_t n, float* out, void* stream) {
   return sq_fill(SQ_F32X2, key, ctr0, n, out, stream);
 }
+
+// ---------------------------------------------------------------- scalar evaluation
+// One 16-byte device buffer per device, allocated on first use and kept.
+static std::mutex g_scalar_mu;
+static std::unordered_map<int, uint64_t*> g_scalar_buf;
+
+static int scalar_eval(uint64_t ctr, uint64_t key, uint64_t out[2]) {
+  SQ_INIT_OR_RETURN();
+  std::lock_guard<std::mutex> g(g_scalar_mu);
+  uint64_t*& buf = g_scalar_buf[device_info().device];
+  hipError_t e = hipSuccess;
+  if (buf == nullptr && (e = hipMalloc((void**)&buf, 256)) != hipSuccess) {
+    buf = nullptr;
+    return fail_hip(e, "scalar buffer allocation");
+  }
+  if ((e = launch_scalar(ctr, key, buf, nullptr)) != hipSuccess) return fail_hip(e, "scalar launch");
+  if ((e = hipMemcpy(out, buf, 16, hipMemcpyDeviceToHost)) != hipSuccess) return fail_hip(e, "scalar copy");
+  return SQ_OK;
+}
+
+int sq32_at(uint64_t ctr, uint64_t key, uint32_t* value) {
+  if (value == nullptr) return fail(SQ_EINVAL, "null value pointer");
+  uint64_t v[2];
+  int rc = scalar_eval(ctr, key, v);
+  if (rc == SQ_OK) *value = (uint32_t)v[0];
+  return rc;
+}
+
+int sq64_at(uint64_t ctr, uint64_t key, uint64_t* value) {
+  if (value == nullptr) return fail(SQ_EINVAL, "null value pointer");
+  uint64_t v[2];
+  int rc = scalar_eval(ctr, key, v);
+  if (rc == SQ_OK) *value = v[1];
+  return rc;
+}
+
+double sq_u128_to_double_scaled(uint64_t lo, uint64_t hi, int pow2_exp) { return round_scaled(lo, hi, pow2_exp); }
 
 // ---------------------------------------------------------------- counter increments other than one
 int sq_fill_strided_cfg(sq_kind kind, uint64_t key, uint64_t ctr0, uint64_t step, uint64_t n, void* out,
@@ -263,6 +302,43 @@ static uint64_t mean_bucket_len(uint32_t m) {
   return 1ull << 20;  // descriptors are on the device; tune by a typical stream length
 }
 
+// With $SQ_DEBUG_VALIDATE set (and not "0"), sq_fill_batch copies the
+// descriptors to the host (synchronising the stream) and rejects a batch
+// whose streams the kernels would skip or whose ranges overlap.
+static bool debug_validate() {
+  const char* e = std::getenv("SQ_DEBUG_VALIDATE");
+  return e && *e && *e != '0';
+}
+
+static int validate_batch_on_host(const uint64_t* keys, const uint64_t* ctr0s, const uint64_t* lens,
+                                  const uint64_t* offs, const uint8_t* kinds, uint32_t m, uint64_t out_bytes,
+                                  hipStream_t s) {
+  (void)keys;
+  (void)ctr0s;
+  std::vector<uint64_t> L(m), O(m);
+  std::vector<uint8_t> K(m);
+  hipError_t e = hipMemcpyAsync(L.data(), lens, 8ull * m, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(O.data(), offs, 8ull * m, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(K.data(), kinds, m, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail_hip(e, "descriptor copy for validation");
+  std::vector<std::pair<uint64_t, uint64_t>> ranges;
+  for (uint32_t i = 0; i < m; ++i) {
+    const int W = kind_bytes(K[i]);
+    if (W == 0) return fail(SQ_EINVAL, "stream " + std::to_string(i) + ": unknown kind");
+    if (O[i] % (uint64_t)kind_align(K[i]) != 0)
+      return fail(SQ_EALIGN, "stream " + std::to_string(i) + ": offset not aligned for its kind");
+    if (O[i] > out_bytes || L[i] > (out_bytes - O[i]) / (uint64_t)W)
+      return fail(SQ_EINVAL, "stream " + std::to_string(i) + ": range past the arena");
+    if (L[i]) ranges.push_back({O[i], O[i] + L[i] * (uint64_t)W});
+  }
+  std::sort(ranges.begin(), ranges.end());
+  for (size_t i = 1; i < ranges.size(); ++i)
+    if (ranges[i].first < ranges[i - 1].second)
+      return fail(SQ_EINVAL, "streams overlap at byte " + std::to_string(ranges[i].first));
+  return SQ_OK;
+}
+
 int sq_fill_batch_cfg(const uint64_t* keys, const uint64_t* ctr0s, const uint64_t* lens, const uint64_t* offs,
                       const uint8_t* kinds, uint32_t m, void* out, uint64_t out_bytes, void* ws, size_t ws_bytes,
                       const sq_launch_cfg* cfg, void* stream) {
@@ -270,6 +346,10 @@ int sq_fill_batch_cfg(const uint64_t* keys, const uint64_t* ctr0s, const uint64_
   if (rc != SQ_OK || m == 0) return rc;
   if (cfg == nullptr || !cfg_valid(SQ_OP_BATCH, *cfg)) return fail(SQ_EINVAL, "invalid batch launch configuration");
   SQ_INIT_OR_RETURN();
+  if (debug_validate()) {
+    rc = validate_batch_on_host(keys, ctr0s, lens, offs, kinds, m, out_bytes, (hipStream_t)stream);
+    if (rc != SQ_OK) return rc;
+  }
   BatchDesc d{keys, ctr0s, lens, offs, kinds, m, (unsigned char*)out, out_bytes};
   hipError_t e = launch_batch(d, ws, *cfg, (hipStream_t)stream);
   return e == hipSuccess ? SQ_OK : fail_hip(e, "batch launch");

@@ -26,6 +26,24 @@ inline int kind_bytes(int kind) {
 }
 inline int kind_align(int kind) { return kind == SQ_U32 || kind == SQ_F32 ? 4 : (kind_bytes(kind) ? 8 : 0); }
 
+// Nearest double (ties to even) of the 128-bit integer (hi:lo) times 2^e:
+// the rounding the reduce applies to its exact sum, on the device in the
+// final reduce kernel and on the host in sq_u128_to_double_scaled.
+__host__ __device__ inline double round_scaled(uint64_t lo, uint64_t hi, int e) {
+  if (hi == 0 && lo < (1ull << 53)) return ldexp((double)lo, e);
+  const int msb = hi ? 127 - __builtin_clzll(hi) : 63 - __builtin_clzll(lo);
+  int s = msb - 52;  // bits dropped, >= 1
+  const unsigned __int128 S = ((unsigned __int128)hi << 64) | lo;
+  uint64_t mant = (uint64_t)(S >> s);
+  const unsigned __int128 rem = S & ((((unsigned __int128)1) << s) - 1);
+  const unsigned __int128 half = ((unsigned __int128)1) << (s - 1);
+  if (rem > half || (rem == half && (mant & 1))) {
+    ++mant;
+    if (mant == (1ull << 53)) { mant >>= 1; ++s; }
+  }
+  return ldexp((double)mant, s + e);
+}
+
 // ---------------------------------------------------------------- device
 struct DeviceInfo {
   int device = -1;
@@ -52,6 +70,9 @@ hipError_t launch_reduce(int kind, uint64_t key, uint64_t ctr0, uint64_t n, sq_s
 // Key-counter mode: out[j] = kind's output at counter ctr under keys[j].
 hipError_t launch_keys(int kind, uint64_t ctr, const uint64_t* keys, uint64_t m, void* out,
                        const sq_launch_cfg& cfg, hipStream_t s);
+
+// squares32 and squares64 at one (ctr, key) into out[0], out[1] (device).
+hipError_t launch_scalar(uint64_t ctr, uint64_t key, uint64_t* out, hipStream_t s);
 
 // Distinct-digit keys from a counter range of squares64 under gen_key.
 hipError_t launch_make_keys(uint64_t gen_key, uint64_t ctr0, uint64_t m, uint64_t* keys,

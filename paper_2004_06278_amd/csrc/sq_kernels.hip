@@ -260,22 +260,6 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a) {
   }
 }
 
-// Nearest double (ties to even) of the 128-bit integer S times 2^e.
-__device__ double round_scaled(uint64_t lo, uint64_t hi, int e) {
-  if (hi == 0 && lo < (1ull << 53)) return ldexp((double)lo, e);
-  const int msb = hi ? 127 - __clzll((long long)hi) : 63 - __clzll((long long)lo);
-  int s = msb - 52;  // bits dropped, >= 1
-  const unsigned __int128 S = ((unsigned __int128)hi << 64) | lo;
-  uint64_t mant = (uint64_t)(S >> s);
-  const unsigned __int128 rem = S & ((((unsigned __int128)1) << s) - 1);
-  const unsigned __int128 half = ((unsigned __int128)1) << (s - 1);
-  if (rem > half || (rem == half && (mant & 1))) {
-    ++mant;
-    if (mant == (1ull << 53)) { mant >>= 1; ++s; }
-  }
-  return ldexp((double)mant, s + e);
-}
-
 // Sums the workgroup partials.  For a split kind with an odd count, the
 // last output (the low half of the counter after the last full pair, whose
 // first Weyl term is y_tail) is added here (split_tail: 4 or 5, else 0).
@@ -290,7 +274,7 @@ __global__ __launch_bounds__(256) void k_reduce_final(const uint64_t* partials, 
     if (split_tail == 5) add128(lo, hi, split_lo_term<5>(y_tail, y_tail + key), 0);
     out->lo = lo;
     out->hi = hi;
-    out->value = round_scaled(lo, hi, e);
+    out->value = sqi::round_scaled(lo, hi, e);
     out->n = n;
   }
 }
@@ -465,6 +449,15 @@ __global__ __launch_bounds__(1024) void k_batch_fill(sqi::BatchDesc d, uint32_t 
   }
 }
 
+// ============================================================== scalar
+// One (ctr, key) in the paper's argument order: both generators.
+__global__ __launch_bounds__(64) void k_scalar(uint64_t ctr, uint64_t key, uint64_t* out) {
+  if (threadIdx.x != 0) return;
+  const uint64_t y = ctr * key;
+  out[0] = sq32(y, y + key);
+  out[1] = sq64(y, y + key);
+}
+
 // ============================================================== key-counter mode
 // Counter fixed, keys varying (the key-counter usage of Section 4): output j
 // comes from keys[j].  Each lane reads 16 / W keys (32 or 16 bytes) and
@@ -541,29 +534,55 @@ KeysKernel keys_kernel(int kind, bool vec) {
 
 // ============================================================== key generation
 // Distinct-digit keys (Section 3, Discussion: the upper 8 hex digits mutually
-// different, the lower 8 too, chosen at random).  Half h of key j draws
-// r = squares64(ctr0 + 2j + h) under gen_key, scales it to an index
-// u = floor(r * N / 2^64) over the N = 16!/8! ordered choices of 8 digits,
-// and reads u's mixed-radix digits (radix 16, 15, ..., 9) as the choices of a
-// partial Fisher-Yates shuffle of 0..15.  The 16-digit list lives in one
-// 64-bit register, one digit per nibble.
-constexpr uint64_t kKeyChoices = 518918400ull;  // 16 * 15 * ... * 9
+// different, the lower 8 too, chosen at random), with an odd least
+// significant digit so that ctr -> ctr*key is a bijection mod 2^64.  The
+// upper half of key j draws r = squares64(ctr0 + 2j) under gen_key, scales it
+// to an index u = floor(r * N / 2^64) over the N = 16!/8! ordered choices of
+// 8 digits and reads u's mixed-radix digits (radix 16, 15, ..., 9) as the
+// choices of a partial Fisher-Yates shuffle of 0..15.  The lower half draws
+// squares64(ctr0 + 2j + 1) and an index over 8 * 15!/8! choices: its radix-8
+// digit picks the odd last digit, which is moved to the front of the list,
+// and shuffle steps 1..7 take the other seven.  The 16-digit list lives in
+// one 64-bit register, one digit per nibble.
+constexpr uint64_t kKeyChoicesHi = 518918400ull;  // 16 * 15 * ... * 9
+constexpr uint64_t kKeyChoicesLo = 259459200ull;  // 8 * 15 * ... * 9
 
-__device__ __forceinline__ uint32_t digits_half(uint64_t r) {
-  uint32_t u = (uint32_t)__umul64hi(r, kKeyChoices);  // < 2^29
-  uint64_t pool = 0xFEDCBA9876543210ull;              // nibble p holds digit p
+// Swaps nibbles i and q of the digit list (a no-op when q == i) and returns
+// the digit that was at q.
+__device__ __forceinline__ uint32_t take_digit(uint64_t& pool, uint32_t i, uint32_t q) {
+  const uint64_t dq = (pool >> (4 * q)) & 15, di = (pool >> (4 * i)) & 15;
+  pool ^= ((dq ^ di) << (4 * i)) | ((dq ^ di) << (4 * q));
+  return (uint32_t)dq;
+}
+
+// Shuffle steps 1..7 on the list (step 0 already taken), most significant
+// digit first.
+__device__ __forceinline__ uint32_t shuffle_digits(uint64_t pool, uint32_t u) {
   uint32_t half = 0;
 #pragma unroll
-  for (uint32_t i = 0; i < 8; ++i) {
+  for (uint32_t i = 1; i < 8; ++i) {
     const uint32_t radix = 16 - i;
     const uint32_t q = i + u % radix;
     u /= radix;
-    const uint64_t dq = (pool >> (4 * q)) & 15, di = (pool >> (4 * i)) & 15;
-    // swap nibbles i and q (a no-op when q == i)
-    pool ^= ((dq ^ di) << (4 * i)) | ((dq ^ di) << (4 * q));
-    half = (half << 4) | (uint32_t)dq;
+    half = (half << 4) | take_digit(pool, i, q);
   }
   return half;
+}
+
+__device__ __forceinline__ uint32_t digits_upper(uint64_t r) {
+  uint32_t u = (uint32_t)__umul64hi(r, kKeyChoicesHi);  // < 2^29
+  uint64_t pool = 0xFEDCBA9876543210ull;                // nibble p holds digit p
+  const uint32_t d0 = take_digit(pool, 0, u % 16);
+  u /= 16;
+  return (d0 << 28) | shuffle_digits(pool, u);
+}
+
+__device__ __forceinline__ uint32_t digits_lower(uint64_t r) {
+  uint32_t u = (uint32_t)__umul64hi(r, kKeyChoicesLo);  // < 2^28
+  uint64_t pool = 0xFEDCBA9876543210ull;
+  const uint32_t odd = take_digit(pool, 0, 2 * (u % 8) + 1);
+  u /= 8;
+  return (shuffle_digits(pool, u) << 4) | odd;
 }
 
 __global__ __launch_bounds__(256) void k_make_keys(uint64_t gen_key, uint64_t ctr0, uint64_t m, uint64_t* keys) {
@@ -572,7 +591,7 @@ __global__ __launch_bounds__(256) void k_make_keys(uint64_t gen_key, uint64_t ct
   for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += stride) {
     const uint64_t y = (ctr0 + 2 * j) * gen_key;
     const uint64_t z = y + gen_key, z2 = z + gen_key;
-    const uint64_t upper = digits_half(sq64(y, z)), lower = digits_half(sq64(z, z2));
+    const uint64_t upper = digits_upper(sq64(y, z)), lower = digits_lower(sq64(z, z2));
     keys[j] = (upper << 32) | lower;
   }
 }
@@ -648,6 +667,11 @@ hipError_t launch_keys(int kind, uint64_t ctr, const uint64_t* keys, uint64_t m,
   if (grid > need) grid = need;
   if (grid == 0) grid = 1;  // the tail still needs a workgroup
   hipLaunchKernelGGL(keys_kernel(kind, vec), dim3((uint32_t)grid), dim3(cfg.block), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_scalar(uint64_t ctr, uint64_t key, uint64_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_scalar, dim3(1), dim3(64), 0, s, ctr, key, out);
   return hipGetLastError();
 }
 

@@ -85,6 +85,9 @@ SIGNATURES = {
     "sq_reduce_workspace_bytes": (ctypes.c_size_t, [_u64]),
     "sq_reduce": (_int, [_int, _u64, _u64, _u64, _vp, _vp, ctypes.c_size_t, _vp]),
     "sq_reduce_cfg": (_int, [_int, _u64, _u64, _u64, _vp, _vp, ctypes.c_size_t, ctypes.POINTER(LaunchCfg), _vp]),
+    "sq32_at": (_int, [_u64, _u64, ctypes.POINTER(_u32)]),
+    "sq64_at": (_int, [_u64, _u64, ctypes.POINTER(_u64)]),
+    "sq_u128_to_double_scaled": (ctypes.c_double, [_u64, _u64, _int]),
     "sq_fill_strided": (_int, [_int, _u64, _u64, _u64, _u64, _vp, _vp]),
     "sq_fill_strided_cfg": (_int, [_int, _u64, _u64, _u64, _u64, _vp, ctypes.POINTER(LaunchCfg), _vp]),
     "sq_reduce_strided": (_int, [_int, _u64, _u64, _u64, _u64, _vp, _vp, ctypes.c_size_t, _vp]),
@@ -244,6 +247,25 @@ def uniform_f64(key, ctr0, n, out=None, stream=None):
 
 
 M64 = (1 << 64) - 1
+
+
+def sq32_at(ctr: int, key: int) -> int:
+    """squares32(ctr, key) in the paper's argument order, evaluated on the GPU."""
+    v = ctypes.c_uint32()
+    check(lib().sq32_at(ctr & M64, key & M64, ctypes.byref(v)))
+    return int(v.value)
+
+
+def sq64_at(ctr: int, key: int) -> int:
+    """squares64(ctr, key) in the paper's argument order, evaluated on the GPU."""
+    v = ctypes.c_uint64()
+    check(lib().sq64_at(ctr & M64, key & M64, ctypes.byref(v)))
+    return int(v.value)
+
+
+def u128_to_double_scaled(total: int, pow2_exp: int) -> float:
+    """Nearest double (ties to even) of total * 2^pow2_exp, total < 2^128."""
+    return float(lib().sq_u128_to_double_scaled(total & M64, (total >> 64) & M64, pow2_exp))
 
 
 def fill_strided(kind: int, key: int, ctr0: int, step: int, n: int, out=None, stream=None,

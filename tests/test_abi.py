@@ -181,6 +181,27 @@ def test_server_argument_checks():
     assert L.sq_server_destroy(None) == 0
 
 
+def test_u128_rounding_helper_matches_oracle(oracle_mod):
+    """The host rounding helper (the same code the final reduce kernel runs)
+    gives the double nearest to S * 2^scale, ties to even, for the kinds'
+    scales: random sums of every magnitude and exact ties."""
+    import numpy as np
+
+    from paper_2004_06278_amd import squares
+
+    g = np.random.Generator(np.random.PCG64(77))
+    cases = [0, 1, 2**53 - 1, 2**53, 2**53 + 1, 2**53 + 3, 2**54 + 2, 2**64 - 1, 2**64, 2**64 + 2**11,
+             2**64 + 2**11 + 2**12, 2**127 + 2**74, 2**128 - 1]
+    for bits in range(1, 129, 3):
+        cases += [int(v) >> (128 - bits) for v in
+                  (int(g.integers(0, 2**64, dtype=np.uint64)) << 64 | int(g.integers(0, 2**64, dtype=np.uint64))
+                   for _ in range(20))]
+    for S in cases:
+        for kind in (0, 1, 3):
+            scale = {0: 0, 1: -24, 3: -53}[kind]
+            assert squares.u128_to_double_scaled(S, scale) == oracle_mod.rounded_value(kind, S), (S, kind)
+
+
 def test_tune_table_roundtrip(tmp_path):
     """The tuning table is host state: set, get, save and load without a GPU."""
     from paper_2004_06278_amd import squares

@@ -251,7 +251,7 @@ def test_make_keys_parity(sq, oracle_mod):
         got = sq.make_keys(gk, c0, m).cpu().numpy().view(np.uint64)
         ref = oracle_mod.make_keys(gk, c0, m)
         assert np.array_equal(got, ref), int(np.nonzero(got != ref)[0][0])
-        assert _distinct_halves(got)
+        assert _distinct_halves(got) and np.all(got & np.uint64(1) == 1)
     win = sq.make_keys(0x9E3779B97F4A7C15, 20, 10).cpu().numpy().view(np.uint64)
     whole = sq.make_keys(0x9E3779B97F4A7C15, 0, 20).cpu().numpy().view(np.uint64)
     assert np.array_equal(win, whole[10:20])
@@ -264,3 +264,39 @@ def test_make_keys_feed_key_counter_mode(sq, oracle_mod):
     got = sq.fill_keys(0, 0, keys).cpu().numpy().view(np.uint32)
     ref = oracle_mod.fill_keys(0, 0, oracle_mod.make_keys(0x6A09E667F3BCC909, 0, 4096))
     assert np.array_equal(got, ref)
+
+
+# ---------------------------------------------------------------- scalar entry points
+def test_scalar_entry_points_paper_argument_order(sq, oracle_mod):
+    """sq32_at / sq64_at take (ctr, key) like the paper's functions and agree
+    with the oracle and with element 0 of a bulk fill called as (key, ctr0)."""
+    g = np.random.Generator(np.random.PCG64(61))
+    pairs = [(0, 0), (1, 2**32 + 1), (1, 2**63), (2**64 - 1, 1), (5, 2**32)]
+    pairs += [(int(a), int(b)) for a, b in g.integers(0, 2**64, size=(40, 2), dtype=np.uint64)]
+    for ctr, key in pairs:
+        assert sq.sq32_at(ctr, key) == oracle_mod.squares32(ctr, key)
+        assert sq.sq64_at(ctr, key) == oracle_mod.squares64(ctr, key)
+    ctr, key = pairs[-1]
+    assert int(sq.sq32_fill(key, ctr, 1).cpu().numpy().view(np.uint32)[0]) == sq.sq32_at(ctr, key)
+    assert int(sq.sq64_fill(key, ctr, 1).cpu().numpy().view(np.uint64)[0]) == sq.sq64_at(ctr, key)
+
+
+def test_debug_validate_rejects_overlap(sq, monkeypatch):
+    """With SQ_DEBUG_VALIDATE set, overlapping streams and streams the kernels
+    would skip are errors at the call; a valid batch still runs."""
+    keys = np.array([1, 2, 3], dtype=np.uint64)
+    ctrs = np.zeros(3, dtype=np.uint64)
+    lens = np.array([100, 100, 100], dtype=np.uint64)
+    kinds = np.zeros(3, dtype=np.uint8)
+    db = sq.batch_to_device(keys, ctrs, lens, np.array([0, 200, 800], dtype=np.uint64), kinds, 4096)
+    monkeypatch.setenv("SQ_DEBUG_VALIDATE", "1")
+    with pytest.raises(sq.SquaresError) as e:
+        sq.fill_batch(db)
+    assert e.value.status == -1 and "overlap" in str(e.value)
+    ok = sq.batch_to_device(keys, ctrs, lens, np.array([0, 400, 800], dtype=np.uint64), kinds, 4096)
+    sq.fill_batch(ok)
+    assert sq.batch_errors(ok) == 0
+    bad = sq.batch_to_device(keys, ctrs, lens, np.array([0, 400, 4000], dtype=np.uint64), kinds, 4096)
+    with pytest.raises(sq.SquaresError) as e:
+        sq.fill_batch(bad)
+    assert e.value.status == -1 and "past the arena" in str(e.value)
