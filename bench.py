@@ -11,14 +11,15 @@ so a step produces 4 * 2^32 numbers.  The timed region holds exactly --steps
 steps with a device synchronisation on both sides; inputs are scalars, so
 nothing is transferred.  The JSON line carries the whole-step rate, each
 kernel's average duration from HIP events on the launch stream, the
-roofline of the dominant kernel, the CPU oracle's rate on a bounded sample,
+roofline of the dominant kernel (and of every kernel, in the step and
+repeated back to back), the CPU oracle's rate on a bounded sample,
 and (unless --no-extras) the split-word variant of squares64, the counter
 modes (increments other than one, key-counter mode, key generation), the
 ragged-batch speedup over per-stream launches and serving latency
 percentiles.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--log2n 32] [--no-extras]
-                       [--extras split,modes,batch,serving] [--no-cpu]
+                       [--extras concurrent,uniform,split,modes,batch,serving] [--no-cpu]
 """
 from __future__ import annotations
 
@@ -106,8 +107,9 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--log2n", type=int, default=32)
     p.add_argument("--no-extras", action="store_true")
-    p.add_argument("--extras", default="split,modes,batch,serving",
-                   help="comma list of extra measurements after the step (split, modes, batch, serving)")
+    p.add_argument("--extras", default="concurrent,uniform,split,modes,batch,serving",
+                   help="comma list of extra measurements after the step "
+                        "(concurrent, uniform, split, modes, batch, serving)")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--calib-copy", action="store_true",
                    help="run a plain 4 GiB device copy first (scales HBM byte counters)")
@@ -185,10 +187,19 @@ def batch_speedup(sq, torch) -> dict:
     n = b.total_outputs
     del db
     torch.cuda.empty_cache()
+    # the same batch with streams starting at random 4-byte offsets
+    bm = W.ragged_batch(seed=3, misalign=True)
+    dbm = sq.batch_to_device(bm.keys, bm.ctr0s, bm.lens, bm.offs, bm.kinds, bm.arena_bytes)
+    planm = sq.BatchPlan(dbm)
+    t_mis = timed(planm.launch, 5)
+    planm.close()
+    del dbm
+    torch.cuda.empty_cache()
     return {"workload": "4096 keys, log-uniform lengths 2^10..2^24, U32/F32", "outputs": n,
             "graph_ms": round(t_plan * 1e3, 3), "per_stream_ms": round(t_each * 1e3, 3),
             "graph_gnum_s": round(n / t_plan / 1e9, 1), "per_stream_gnum_s": round(n / t_each / 1e9, 1),
-            "speedup": round(t_each / t_plan, 2)}
+            "speedup": round(t_each / t_plan, 2), "graph_gb_s": round(4 * n / t_plan / 1e9, 1),
+            "misaligned_graph_ms": round(t_mis * 1e3, 3)}
 
 
 def split_words(sq, torch, key: int, ctr0: int, n: int, per_op_ms: dict) -> dict:
@@ -233,6 +244,61 @@ def _event_ms(torch, fn, reps: int = 10, warm: int = 2) -> float:
         evs.append((a, b))
     torch.cuda.synchronize()
     return sum(a.elapsed_time(b) for a, b in evs) / len(evs)
+
+
+def concurrent_step(sq, torch, key: int, ctr0: int, n: int, serial_ms: float, steps: int = 10) -> dict:
+    """The same step with the two fills on one stream and the two fused sums
+    on another (HBM-bound and VALU-bound work overlapping), timed over
+    `steps` steps like the serial step."""
+    out32 = torch.empty(n, dtype=torch.uint32, device="cuda")
+    out64 = torch.empty(n, dtype=torch.uint64, device="cuda")
+    r1, r2 = sq.result_tensor(), sq.result_tensor()
+    w1, w2 = sq.reduce_workspace(n), sq.reduce_workspace(n)
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    main = torch.cuda.current_stream()
+
+    def step():
+        start = torch.cuda.Event()
+        start.record(main)
+        sa.wait_event(start)
+        sb.wait_event(start)
+        sq.fill(sq.U32, key, ctr0, n, out=out32, stream=sa)
+        sq.fill(sq.U64, key, ctr0, n, out=out64, stream=sa)
+        sq.reduce_async(sq.F32, key, ctr0, n, r1, w1, stream=sb)
+        sq.reduce_async(sq.F64, key, ctr0, n, r2, w2, stream=sb)
+        ea, eb = torch.cuda.Event(), torch.cuda.Event()
+        ea.record(sa)
+        eb.record(sb)
+        main.wait_event(ea)
+        main.wait_event(eb)
+
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    del out32, out64
+    torch.cuda.empty_cache()
+    return {"ms_per_step": round(ms, 4), "gnum_s": round(4 * n / (ms * 1e-3) / 1e9, 1),
+            "vs_serial_step": round(serial_ms / ms, 3), "streams": 2}
+
+
+def uniform_fills(sq, torch, key: int, ctr0: int, n: int) -> dict:
+    """The uniform fills over the same n counters: F32 (16 GiB) and F64
+    (32 GiB), conversion fused into the generating kernel."""
+    r = {}
+    for name, kind, W in (("uniform_f32", sq.F32, 4), ("uniform_f64", sq.F64, 8)):
+        out = torch.empty(n * W, dtype=torch.uint8, device="cuda")
+        ms = _event_ms(torch, lambda: sq.fill(kind, key, ctr0, n, out=out))
+        gbs = W * n / (ms * 1e-3) / 1e9
+        r[name] = {"n": n, "ms": round(ms, 4), "gnum_s": round(n / (ms * 1e-3) / 1e9, 1), "gb_s": round(gbs, 1),
+                   "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+        del out
+        torch.cuda.empty_cache()
+    return r
 
 
 def counter_modes(sq, torch, key: int, ctr0: int, n: int, per_op_ms: dict) -> dict:
@@ -335,6 +401,7 @@ def main() -> int:
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     per_op_ms = {name: sum(a.elapsed_time(b) for a, b in ev[name]) / len(ev[name]) for name in ev}
+    per_op_sorted = {name: sorted(a.elapsed_time(b) for a, b in ev[name]) for name in ev}
     value = 4 * n / (ms_per_step * 1e-3) / 1e9
 
     # spot check of the timed outputs against the oracle (outside the timed region)
@@ -351,15 +418,22 @@ def main() -> int:
     s64, v64, _ = sq.read_result(res64)
     assert abs(v32 / n - 0.5) < 1e-3 and abs(v64 / n - 0.5) < 1e-3
 
-    def hbm_roof(name, nbytes):
-        ms = per_op_ms[name]
+    # measured store ceiling at the same size: torch's plain fill kernel over
+    # the 16 GiB output buffer (outside the timed region)
+    store_ms = _event_ms(torch, lambda: out32.fill_(1), reps=5)
+    store_gbs = 4 * n / (store_ms * 1e-3) / 1e9
+
+    def hbm_roof(name, nbytes, ms_by_op=per_op_ms):
+        ms = ms_by_op[name]
         gbs = nbytes / (ms * 1e-3) / 1e9
         return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": name, "avg_ms": round(ms, 4), "algorithmic_bytes": nbytes}
+                "kernel": name, "avg_ms": round(ms, 4), "algorithmic_bytes": nbytes,
+                "measured_store_ceiling_gbs": round(store_gbs, 1),
+                "frac_of_store_ceiling": round(gbs / store_gbs, 4)}
 
-    def alu_roof(name, slots):
-        ms = per_op_ms[name]
+    def alu_roof(name, slots, ms_by_op=per_op_ms):
+        ms = ms_by_op[name]
         rate = slots * n / (ms * 1e-3)
         return {"bound": "alu", "achieved": round(rate / 1e12, 3), "peak": round(ALU_PEAK_SLOTS / 1e12, 3),
                 "unit": "T VALU-slot/s", "frac": round(rate / ALU_PEAK_SLOTS, 4), "traffic": None,
@@ -370,6 +444,17 @@ def main() -> int:
         "sq64_fill": hbm_roof("sq64_fill", 8 * n),
         "fused_f32_sum": alu_roof("fused_f32_sum", SLOTS["sq32"] + SLOTS["sum_f32"]),
         "fused_f64_sum": alu_roof("fused_f64_sum", SLOTS["sq64"] + SLOTS["sum_f64"]),
+    }
+    # The same kernels repeated back to back (10 timed after 3 untimed): in the
+    # step, a kernel that follows one of the other class starts while the
+    # shader clock is still moving between the memory-bound and the
+    # compute-bound operating points, which costs up to ~0.5 ms per switch.
+    steady_ms = {name: _event_ms(torch, fn, reps=10, warm=3) for name, fn in ops}
+    rooflines_steady = {
+        "sq32_fill": hbm_roof("sq32_fill", 4 * n, steady_ms),
+        "sq64_fill": hbm_roof("sq64_fill", 8 * n, steady_ms),
+        "fused_f32_sum": alu_roof("fused_f32_sum", SLOTS["sq32"] + SLOTS["sum_f32"], steady_ms),
+        "fused_f64_sum": alu_roof("fused_f64_sum", SLOTS["sq64"] + SLOTS["sum_f64"], steady_ms),
     }
     dominant = max(per_op_ms, key=per_op_ms.get)
     traffic_file = os.path.join(ROOT, "profiles", "traffic.json")
@@ -401,12 +486,18 @@ def main() -> int:
                    "parallelism": "single GPU"},
         "per_kernel_gnum_s": {k: round(n / (v * 1e-3) / 1e9, 1) for k, v in per_op_ms.items()},
         "per_kernel_ms": {k: round(v, 4) for k, v in per_op_ms.items()},
+        "per_kernel_median_min_ms": {k: [round(v[len(v) // 2], 4), round(v[0], 4)] for k, v in per_op_sorted.items()},
         "roofline": rooflines[dominant],
         "rooflines": rooflines,
+        "rooflines_steady": rooflines_steady,
     }
     del out32, out64
     torch.cuda.empty_cache()
     extras = set() if args.no_extras else set(args.extras.split(","))
+    if "concurrent" in extras:
+        line["concurrent_step"] = concurrent_step(sq, torch, key, ctr0, n, ms_per_step)
+    if "uniform" in extras:
+        line["uniform_fills"] = uniform_fills(sq, torch, key, ctr0, n)
     if "split" in extras:
         line["split_words"] = split_words(sq, torch, key, ctr0, n, per_op_ms)
     if "modes" in extras:

@@ -115,13 +115,19 @@ int sq_uniform_f32x2(uint64_t key, uint64_t ctr0, uint64_t n, float *out, void *
  * Launch configurations (chosen by the autotuner; explicit for tests).
  * ------------------------------------------------------------------------ */
 typedef struct {
-    uint32_t block;        /* threads per workgroup: 256, 512 or 1024 */
-    uint32_t unroll;       /* 16-byte vectors per lane per step: 4 or 8 (fill);
+    uint32_t block;        /* threads per workgroup: 64, 128, 256, 512 or 1024 (fill);
+                              256, 512 or 1024 (batch); reduce uses 256 */
+    uint32_t unroll;       /* 16-byte vectors per lane per chunk: 1, 2, 4 or 8 (fill);
                               outputs per lane per step for reduce: 1, 2 or 4 */
     uint32_t grid_per_cu;  /* workgroups per compute unit (grid = CUs * this), 1..64 */
-    uint32_t xcd_map;      /* 0: consecutive chunks round-robin over the 8 XCDs;
-                              1: each XCD takes one contiguous eighth of the range */
-    uint32_t tile_log2;    /* batch only: outputs per tile = 2^tile_log2, 12..24 */
+    uint32_t xcd_map;      /* fill chunk order.  0: grid-stride, consecutive chunks
+                              round-robin over the 8 XCDs; 1: grid-stride, each XCD
+                              takes one contiguous eighth of the range; 2: one chunk
+                              per workgroup (grid = chunks, grid_per_cu unused) */
+    uint32_t tile_log2;    /* batch only: outputs per tile = 2^tile_log2, 10..24
+                              (batch xcd_map: 0 persistent grid, static interleave;
+                              1 persistent grid, tiles taken from a queue in order;
+                              2 one tile per workgroup) */
 } sq_launch_cfg;
 
 /* Operation classes the tuning table is keyed by. */
@@ -205,8 +211,10 @@ int sq_reduce_strided_cfg(sq_kind kind, uint64_t key, uint64_t ctr0, uint64_t st
  * buffer of m elements aligned to the element size.  When both are 16-byte
  * aligned the kernel reads and writes whole 16-byte vectors; otherwise it
  * works one element per lane.  m == 0 returns SQ_OK without a launch.  The
- * _cfg variant takes `block` and `grid_per_cu` from cfg (validated as a fill
- * configuration; `unroll`, `xcd_map` and `tile_log2` are ignored).
+ * _cfg variant takes `block`, `grid_per_cu` and `xcd_map` from cfg
+ * (validated as a fill configuration; xcd_map 2 launches one workgroup per
+ * block of work instead of a grid-stride loop; `unroll` and `tile_log2` are
+ * ignored).
  * ------------------------------------------------------------------------ */
 int sq_fill_keys(sq_kind kind, uint64_t ctr, const uint64_t *keys, uint64_t m, void *out,
                  void *stream);
@@ -309,7 +317,7 @@ typedef struct {
     uint32_t max_slots;         /* admitted-but-unreleased requests, 1..65536 */
     uint64_t chunk_cap;         /* outputs of one request per tick (>= 4096) */
     uint32_t n_streams;         /* concurrent ticks, 1..8 */
-    uint32_t tile_log2;         /* tile of the tick kernel (0 = tuned) */
+    uint32_t tile_log2;         /* tile of the tick kernel, 10..24 (0 = 14) */
 } sq_server_cfg;
 
 /* submit() flags */

@@ -96,7 +96,8 @@ struct BatchHdr {
   uint64_t total_tiles;
   uint32_t errors;
   uint32_t m;
-  uint64_t pad[6];
+  uint64_t next_tile;  // tile queue of the dynamic batch order (reset by the scan)
+  uint64_t pad[5];
 };
 static_assert(sizeof(BatchHdr) == 64, "header is 64 bytes");
 uint64_t batch_max_tiles(uint32_t m, uint64_t out_bytes);

@@ -95,7 +95,12 @@ __device__ __forceinline__ void fill_chunk(const FillArgs& a, uint64_t c) {
 template <int K, int U, bool S>
 __global__ __launch_bounds__(1024) void k_fill(FillArgs a) {
   fill_edges<K>(a);
-  if (a.xcd_map == 0) {
+  if (a.xcd_map == 2) {
+    // one chunk per workgroup (grid = nchunks): workgroups retire and the
+    // next ones start in dispatch order, so the chip writes one narrow
+    // moving window of the output
+    if (blockIdx.x < a.nchunks) fill_chunk<K, U, S>(a, blockIdx.x);
+  } else if (a.xcd_map == 0) {
 #pragma unroll 1
     for (uint64_t c = blockIdx.x; c < a.nchunks; c += gridDim.x) fill_chunk<K, U, S>(a, c);
   } else {
@@ -113,7 +118,12 @@ __global__ __launch_bounds__(1024) void k_fill(FillArgs a) {
 typedef void (*FillKernel)(FillArgs);
 template <int K, bool S>
 FillKernel fill_kernel_for(uint32_t unroll) {
-  return unroll == 4 ? k_fill<K, 4, S> : k_fill<K, 8, S>;
+  switch (unroll) {
+    case 1: return k_fill<K, 1, S>;
+    case 2: return k_fill<K, 2, S>;
+    case 4: return k_fill<K, 4, S>;
+    default: return k_fill<K, 8, S>;
+  }
 }
 
 template <bool S>
@@ -357,6 +367,7 @@ __global__ __launch_bounds__(1024) void k_batch_scan(sqi::BatchDesc d, const uin
     hdr->total_tiles = fits ? part[B - 1] : 0;
     hdr->m = m;
     hdr->errors = fits ? errs : m;
+    hdr->next_tile = 0;
   }
 }
 
@@ -421,31 +432,51 @@ __device__ __forceinline__ void fill_range(uint64_t key, uint64_t ctr, uint64_t 
   }
 }
 
-// Persistent: workgroup g takes tiles g, g + grid, g + 2*grid, ..., so the
-// workgroups running at any moment write neighbouring parts of the arena;
-// the stream of a tile is one load from the tile map.
-__global__ __launch_bounds__(1024) void k_batch_fill(sqi::BatchDesc d, uint32_t lg, const sqi::BatchHdr* hdr,
-                                                     const uint64_t* ts, const uint32_t* map) {
-  const uint64_t total = hdr->total_tiles;
+// One tile: the stream is one load from the tile map.
+__device__ __forceinline__ void batch_tile(const sqi::BatchDesc& d, uint32_t lg, const uint64_t* ts,
+                                           const uint32_t* map, uint64_t t) {
   const uint64_t T = 1ull << lg;
+  const uint32_t s = map[t];
+  const uint64_t off = (t - ts[s]) << lg;
+  const uint64_t len = d.lens[s];
+  const uint64_t cnt = len - off < T ? len - off : T;
+  const uint32_t kind = d.kinds[s];
+  const bool split = kind > 3;  // two elements per counter; tiles hold an even count
+  const uint64_t key = d.keys[s], ctr = d.ctr0s[s] + (split ? off >> 1 : off);
+  unsigned char* p = d.out + d.offs[s] + off * ((kind == 2 || kind == 3) ? 8u : 4u);
+  switch (kind) {
+    case 0: fill_range<0>(key, ctr, cnt, p); break;
+    case 1: fill_range<1>(key, ctr, cnt, p); break;
+    case 2: fill_range<2>(key, ctr, cnt, p); break;
+    case 3: fill_range<3>(key, ctr, cnt, p); break;
+    case 4: fill_range<4>(key, ctr, cnt, p); break;
+    default: fill_range<5>(key, ctr, cnt, p); break;
+  }
+}
+
+// order 0: workgroup g takes tiles g, g + grid, g + 2*grid, ..., so the
+// workgroups running at any moment write neighbouring parts of the arena
+// (with a grid as large as the tile bound, one tile each: order 2).
+// order 1: a persistent grid takes tiles from a queue in tile order, so
+// workgroups that finish early take more (the write front stays narrow and
+// no workgroup idles while another still has a static share left).
+__global__ __launch_bounds__(1024) void k_batch_fill(sqi::BatchDesc d, uint32_t lg, uint32_t order,
+                                                     sqi::BatchHdr* hdr, const uint64_t* ts, const uint32_t* map) {
+  const uint64_t total = hdr->total_tiles;
+  if (order != 1) {
 #pragma unroll 1
-  for (uint64_t t = blockIdx.x; t < total; t += gridDim.x) {
-    const uint32_t s = map[t];
-    const uint64_t off = (t - ts[s]) << lg;
-    const uint64_t len = d.lens[s];
-    const uint64_t cnt = len - off < T ? len - off : T;
-    const uint32_t kind = d.kinds[s];
-    const bool split = kind > 3;  // two elements per counter; tiles hold an even count
-    const uint64_t key = d.keys[s], ctr = d.ctr0s[s] + (split ? off >> 1 : off);
-    unsigned char* p = d.out + d.offs[s] + off * ((kind == 2 || kind == 3) ? 8u : 4u);
-    switch (kind) {
-      case 0: fill_range<0>(key, ctr, cnt, p); break;
-      case 1: fill_range<1>(key, ctr, cnt, p); break;
-      case 2: fill_range<2>(key, ctr, cnt, p); break;
-      case 3: fill_range<3>(key, ctr, cnt, p); break;
-      case 4: fill_range<4>(key, ctr, cnt, p); break;
-      default: fill_range<5>(key, ctr, cnt, p); break;
-    }
+    for (uint64_t t = blockIdx.x; t < total; t += gridDim.x) batch_tile(d, lg, ts, map, t);
+    return;
+  }
+  __shared__ uint64_t s_tile;
+#pragma unroll 1
+  while (true) {
+    if (threadIdx.x == 0) s_tile = atomicAdd((unsigned long long*)&hdr->next_tile, 1ull);
+    __syncthreads();
+    const uint64_t t = s_tile;
+    __syncthreads();  // every lane has read s_tile before lane 0 overwrites it
+    if (t >= total) break;
+    batch_tile(d, lg, ts, map, t);
   }
 }
 
@@ -648,8 +679,14 @@ hipError_t launch_fill(int kind, uint64_t key, uint64_t ctr0, uint64_t n, void* 
   uint64_t grid = (uint64_t)device_info().cus * cfg.grid_per_cu;
   if (grid > a.nchunks) grid = a.nchunks;
   a.xcd_map = cfg.xcd_map;
-  if (a.xcd_map && grid >= 8) grid &= ~7ull;  // XCD-contiguous order needs a multiple of 8
-  else a.xcd_map = 0;
+  if (a.xcd_map == 2 && a.nchunks < (1ull << 31)) {
+    grid = a.nchunks;  // one chunk per workgroup
+  } else if (a.xcd_map == 1 && grid >= 8) {
+    grid &= ~7ull;     // XCD-contiguous order needs a multiple of 8
+  } else {
+    if (a.xcd_map == 2) grid = std::min<uint64_t>(a.nchunks, (uint64_t)device_info().cus * 64);
+    a.xcd_map = 0;
+  }
   if (grid == 0) grid = 1;                      // the head/tail elements still need a workgroup
   const FillKernel k = step == 1 ? fill_kernel<false>(kind, cfg.unroll) : fill_kernel<true>(kind, cfg.unroll);
   hipLaunchKernelGGL(k, dim3((uint32_t)grid), dim3(cfg.block), 0, s, a);
@@ -664,7 +701,7 @@ hipError_t launch_keys(int kind, uint64_t ctr, const uint64_t* keys, uint64_t m,
   const uint64_t work = vec ? a.nvec : m;
   uint64_t grid = (uint64_t)device_info().cus * cfg.grid_per_cu;
   const uint64_t need = (work + cfg.block - 1) / cfg.block;
-  if (grid > need) grid = need;
+  if (grid > need || (cfg.xcd_map == 2 && need < (1ull << 31))) grid = need;  // 2: one step per lane
   if (grid == 0) grid = 1;  // the tail still needs a workgroup
   hipLaunchKernelGGL(keys_kernel(kind, vec), dim3((uint32_t)grid), dim3(cfg.block), 0, s, a);
   return hipGetLastError();
@@ -735,10 +772,10 @@ hipError_t launch_reduce(int kind, uint64_t key, uint64_t ctr0, uint64_t n, sq_s
 }
 
 // Batch workspace: header, tile_start[m+1] (u64), tile map (u32, one per
-// tile).  Tiles are at least 2^12 outputs of at least 4 bytes, and streams
+// tile).  Tiles are at least 2^10 outputs of at least 4 bytes, and streams
 // lie inside the arena without overlap, so there are at most
-// m + out_bytes / 2^14 tiles.
-uint64_t batch_max_tiles(uint32_t m, uint64_t out_bytes) { return (uint64_t)m + (out_bytes >> 14) + 1; }
+// m + out_bytes / 2^12 tiles.
+uint64_t batch_max_tiles(uint32_t m, uint64_t out_bytes) { return (uint64_t)m + (out_bytes >> 12) + 1; }
 
 size_t batch_ws_bytes(uint32_t m, uint64_t out_bytes) {
   const size_t b = sizeof(BatchHdr) + 8ull * ((size_t)m + 1) + 4ull * batch_max_tiles(m, out_bytes);
@@ -758,8 +795,12 @@ static hipError_t launch_batch_body(const BatchDesc& d, const uint32_t* m_dev, v
                      (const uint64_t*)ts, map);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const uint32_t grid = (uint32_t)device_info().cus * cfg.grid_per_cu;
-  hipLaunchKernelGGL(k_batch_fill, dim3(grid), dim3(cfg.block), 0, s, d, cfg.tile_log2, (const BatchHdr*)hdr,
+  // xcd_map 2: one tile per workgroup, grid = the tile bound (workgroups
+  // past the scanned total exit at once); otherwise a persistent grid that
+  // takes tiles in a static interleave (0) or from the queue (1)
+  const uint32_t grid = cfg.xcd_map == 2 ? (uint32_t)std::min<uint64_t>(max_tiles, 0x7FFFFFFFull)
+                                         : (uint32_t)device_info().cus * cfg.grid_per_cu;
+  hipLaunchKernelGGL(k_batch_fill, dim3(grid), dim3(cfg.block), 0, s, d, cfg.tile_log2, cfg.xcd_map, hdr,
                      (const uint64_t*)ts, (const uint32_t*)map);
   return hipGetLastError();
 }

@@ -327,7 +327,7 @@ int sq_server_create(const sq_server_cfg* cfg, sq_server** out) {
   if (cfg == nullptr || out == nullptr) return fail(SQ_EINVAL, "null cfg or server pointer");
   *out = nullptr;
   if (cfg->hbm_budget_bytes < 4096 || cfg->max_slots < 1 || cfg->max_slots > 65536 || cfg->chunk_cap < 4096 ||
-      cfg->n_streams < 1 || cfg->n_streams > 8 || (cfg->tile_log2 != 0 && (cfg->tile_log2 < 12 || cfg->tile_log2 > 24)))
+      cfg->n_streams < 1 || cfg->n_streams > 8 || (cfg->tile_log2 != 0 && (cfg->tile_log2 < 10 || cfg->tile_log2 > 24)))
     return fail(SQ_EINVAL, "server configuration out of range");
   int rc = ensure_init();
   if (rc != SQ_OK) return rc;
@@ -335,7 +335,10 @@ int sq_server_create(const sq_server_cfg* cfg, sq_server** out) {
   s->cfg = *cfg;
   s->cfg.chunk_cap &= ~1ull;  // chunks of split kinds must start at a low word
   s->device = device_info().device;
-  s->lcfg = tuned_cfg(SQ_OP_BATCH, SQ_U32, cfg->chunk_cap);
+  // Ticks are many small batches over a large arena: a persistent grid with
+  // the static tile interleave (no tile-bound grid, no queue) and 2^14-output
+  // tiles gave the lowest latency in open-loop runs on MI355X.
+  s->lcfg = sq_launch_cfg{256, 1, 4, 0, 14};
   if (cfg->tile_log2) s->lcfg.tile_log2 = cfg->tile_log2;
   s->arena = new Arena(cfg->hbm_budget_bytes);
   hipError_t e = hipMalloc((void**)&s->arena_dev, cfg->hbm_budget_bytes);

@@ -47,11 +47,11 @@ bool cfg_valid(sq_op op, const sq_launch_cfg& c) {
   if (c.grid_per_cu < 1 || c.grid_per_cu > 64) return false;
   switch (op) {
     case SQ_OP_FILL:
-      return in(c.block, {256, 512, 1024}) && in(c.unroll, {4, 8}) && c.xcd_map <= 1;
+      return in(c.block, {64, 128, 256, 512, 1024}) && in(c.unroll, {1, 2, 4, 8}) && c.xcd_map <= 2;
     case SQ_OP_REDUCE:
       return in(c.unroll, {1, 2, 4});
     case SQ_OP_BATCH:
-      return in(c.block, {256, 512, 1024}) && c.tile_log2 >= 12 && c.tile_log2 <= 24;
+      return in(c.block, {64, 128, 256, 512, 1024}) && c.tile_log2 >= 10 && c.tile_log2 <= 24 && c.xcd_map <= 2;
   }
   return false;
 }
@@ -59,12 +59,18 @@ bool cfg_valid(sq_op op, const sq_launch_cfg& c) {
 sq_launch_cfg default_cfg(sq_op op, int kind, uint64_t n) {
   (void)n;
   switch (op) {
-    // 1024 threads x 8 vectors: each workgroup step writes 128 KiB
-    // contiguous, the shape that reached the HBM store ceiling in a
-    // store-only kernel on MI355X
-    case SQ_OP_FILL: return sq_launch_cfg{1024, 8, 16, 0, 16};
+    // One 4 KiB chunk per workgroup (grid = chunks): the fastest fill shapes
+    // measured on MI355X.  Small one-shot chunks keep the write front narrow
+    // and let retiring workgroups be replaced anywhere.  squares32 kinds do
+    // more VALU work per byte and do best with one wave per workgroup and 4
+    // vectors per lane; squares64 kinds with 256 lanes and one vector each.
+    case SQ_OP_FILL:
+      return (kind == SQ_U32 || kind == SQ_F32) ? sq_launch_cfg{64, 4, 1, 2, 16} : sq_launch_cfg{256, 1, 1, 2, 16};
     case SQ_OP_REDUCE: return sq_launch_cfg{256, 4, 8, 0, 16};
-    default: return sq_launch_cfg{512, 1, 4, 0, 16};
+    // a persistent grid of two 256-lane workgroups per CU taking tiles of
+    // 2^16 outputs from the queue: the fastest ragged-batch shape measured
+    // on MI355X (dynamic balance with few descriptor loads per byte)
+    default: return sq_launch_cfg{256, 1, 2, 1, 16};
   }
 }
 
@@ -287,22 +293,27 @@ int sq_autotune(uint32_t op_mask, uint64_t max_bytes, const char* save_path) {
         // alternation with the incumbent and replaces it when its median is
         // 2% lower (below timing noise) and its bytes equal the reference's.
         sq_launch_cfg best_c = ref;
-        for (uint32_t blk : {256u, 512u, 1024u})
+        // candidates: one chunk per workgroup for every block and unroll,
+        // and the grid-stride orders for the larger shapes
+        std::vector<sq_launch_cfg> cands;
+        for (uint32_t blk : {64u, 128u, 256u, 512u, 1024u})
+          for (uint32_t u : {1u, 2u, 4u, 8u}) cands.push_back(sq_launch_cfg{blk, u, 1, 2, 16});
+        for (uint32_t blk : {256u, 1024u})
           for (uint32_t u : {4u, 8u})
-            for (uint32_t g : {1u, 2u, 4u, 8u, 16u, 32u, 64u})
-              for (uint32_t x : {0u, 1u}) {
-                const sq_launch_cfg c{blk, u, g, x, 16};
-                float ms_inc = 0, ms = 0;
-                const sq_launch_cfg inc = best_c;
-                e = time_pair(
-                    S, [&] { return launch_fill(kind, key, ctr0, n, (unsigned char*)S.b, inc, S.s); },
-                    [&] { return launch_fill(kind, key, ctr0, n, (unsigned char*)S.b, c, S.s); }, 5, &ms_inc, &ms);
-                if (e != hipSuccess) break;
-                bool same = false;
-                if ((e = same_bytes(S, n * W, &same)) != hipSuccess) break;
-                report("fill", kind, b, n, c, ms, same);
-                if (same && ms < 0.98f * ms_inc) best_c = c;
-              }
+            for (uint32_t g : {1u, 4u, 16u, 64u})
+              for (uint32_t x : {0u, 1u}) cands.push_back(sq_launch_cfg{blk, u, g, x, 16});
+        for (const sq_launch_cfg& c : cands) {
+          float ms_inc = 0, ms = 0;
+          const sq_launch_cfg inc = best_c;
+          e = time_pair(
+              S, [&] { return launch_fill(kind, key, ctr0, n, (unsigned char*)S.b, inc, S.s); },
+              [&] { return launch_fill(kind, key, ctr0, n, (unsigned char*)S.b, c, S.s); }, 5, &ms_inc, &ms);
+          if (e != hipSuccess) break;
+          bool same = false;
+          if ((e = same_bytes(S, n * W, &same)) != hipSuccess) break;
+          report("fill", kind, b, n, c, ms, same);
+          if (same && ms < 0.98f * ms_inc) best_c = c;
+        }
         if (e != hipSuccess) break;
         report("fill-chosen", kind, b, n, best_c, 0.f, true);
         set_entry(SQ_OP_FILL, kind, b, best_c);
@@ -399,23 +410,29 @@ int sq_autotune(uint32_t op_mask, uint64_t max_bytes, const char* save_path) {
         BatchDesc d{dk, dc, dl, dof, dkd, m, (unsigned char*)S.a, budget};
         e = launch_batch(d, ws, ref, S.s);
       }
-      for (uint32_t tl : {14u, 16u, 18u, 20u}) {
-        for (uint32_t blk : {256u, 512u, 1024u}) {
-          for (uint32_t g : {2u, 4u, 8u, 16u}) {
-            if (e != hipSuccess) break;
-            const sq_launch_cfg c{blk, 1, g, 0, tl};
-            const sq_launch_cfg inc = best_c;
-            BatchDesc d{dk, dc, dl, dof, dkd, m, (unsigned char*)S.b, budget};
-            float ms_inc = 0, ms = 0;
-            e = time_pair(S, [&] { return launch_batch(d, ws, inc, S.s); },
-                          [&] { return launch_batch(d, ws, c, S.s); }, 5, &ms_inc, &ms);
-            if (e != hipSuccess) break;
-            bool same = false;
-            if ((e = same_bytes(S, used, &same)) != hipSuccess) break;
-            report("batch", -1, b, pos, c, ms, same);
-            if (same && ms < 0.98f * ms_inc) best_c = c;
-          }
-        }
+      // candidates: one tile per workgroup with small tiles, and persistent
+      // grids with larger ones
+      std::vector<sq_launch_cfg> cands;
+      for (uint32_t tl : {10u, 11u, 12u, 13u})
+        for (uint32_t blk : {64u, 128u, 256u}) cands.push_back(sq_launch_cfg{blk, 1, 1, 2, tl});
+      for (uint32_t tl : {14u, 16u, 18u})
+        for (uint32_t blk : {256u, 1024u})
+          for (uint32_t g : {2u, 4u, 8u, 16u}) cands.push_back(sq_launch_cfg{blk, 1, g, 0, tl});
+      for (uint32_t tl : {13u, 14u, 15u, 16u, 17u, 18u})
+        for (uint32_t blk : {256u, 512u})
+          for (uint32_t g : {1u, 2u, 4u}) cands.push_back(sq_launch_cfg{blk, 1, g, 1, tl});
+      for (const sq_launch_cfg& c : cands) {
+        if (e != hipSuccess) break;
+        const sq_launch_cfg inc = best_c;
+        BatchDesc d{dk, dc, dl, dof, dkd, m, (unsigned char*)S.b, budget};
+        float ms_inc = 0, ms = 0;
+        e = time_pair(S, [&] { return launch_batch(d, ws, inc, S.s); },
+                      [&] { return launch_batch(d, ws, c, S.s); }, 5, &ms_inc, &ms);
+        if (e != hipSuccess) break;
+        bool same = false;
+        if ((e = same_bytes(S, used, &same)) != hipSuccess) break;
+        report("batch", -1, b, pos, c, ms, same);
+        if (same && ms < 0.98f * ms_inc) best_c = c;
       }
       if (e == hipSuccess) report("batch-chosen", -1, b, pos, best_c, 0.f, true);
       hipError_t fe = hipFree(desc);

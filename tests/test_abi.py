@@ -76,10 +76,13 @@ def test_fill_argument_checks():
     assert rc == -1
     assert L.sq_fill(0, 1, 0, 0, None, None) == 0          # n == 0: nothing to do
     assert L.sq32_fill(1, 0, 0, None, None) == 0
-    bad = squares.LaunchCfg(128, 8, 16, 0, 16)
+    bad = squares.LaunchCfg(96, 8, 16, 0, 16)
     rc, _ = _rc(L.sq_fill_cfg, 0, 1, 0, 10, FAKE, bad, None)
     assert rc == -1
-    bad = squares.LaunchCfg(256, 3, 16, 0, 16)             # unroll must be 4 or 8
+    bad = squares.LaunchCfg(256, 3, 16, 0, 16)             # unroll must be 1, 2, 4 or 8
+    rc, _ = _rc(L.sq_fill_cfg, 0, 1, 0, 10, FAKE, bad, None)
+    assert rc == -1
+    bad = squares.LaunchCfg(256, 4, 16, 3, 16)             # chunk orders 0, 1, 2
     rc, _ = _rc(L.sq_fill_cfg, 0, 1, 0, 10, FAKE, bad, None)
     assert rc == -1
 
@@ -142,6 +145,10 @@ def test_batch_argument_checks():
     a = list(args); a[9] = ws - 256
     assert _rc(L.sq_fill_batch, *a)[0] == -3
     assert L.sq_batch_workspace_bytes(m, 2 * arena) > ws       # the tile map grows with the arena
+    good = squares.LaunchCfg(128, 1, 1, 2, 11)
+    assert _rc(L.sq_fill_batch_cfg, *(args[:10] + [squares.LaunchCfg(128, 1, 1, 2, 9), None]))[0] == -1  # tile < 2^10
+    assert _rc(L.sq_fill_batch_cfg, *(args[:10] + [squares.LaunchCfg(128, 1, 1, 3, 11), None]))[0] == -1  # order 3
+    assert good.as_dict()["tile_log2"] == 11
 
 
 def test_per_stream_host_checks():

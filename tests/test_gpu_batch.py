@@ -31,16 +31,19 @@ def test_batch_small_random(sq, oracle_mod, seed):
     b = W.small_random_batch(seed=seed, m=300, max_len=20000, kinds=(0, 1, 2, 3, 4, 5))
     ref = _oracle_arena(oracle_mod, b)
     db = sq.batch_to_device(b.keys, b.ctr0s, b.lens, b.offs, b.kinds, b.arena_bytes)
-    for tl in (12, 13, 16, 24):
-        for block in (256, 1024):
-            for gpc in (1, 8):
-                c = sq.cfg(block=block, grid_per_cu=gpc, tile_log2=tl)
-                log(f"batch seed={seed} m={b.m} cfg={c.as_dict()}")
-                db.out.zero_()
-                sq.fill_batch(db, launch_cfg=c)
-                got = to_host_bytes(db.out)[: b.arena_bytes]
-                assert got.tobytes() == ref.tobytes(), (c.as_dict(), first_diff(got, ref))
-                assert sq.batch_errors(db) == 0
+    cfgs = [sq.cfg(block=blk, grid_per_cu=gpc, tile_log2=tl) for tl in (12, 13, 16, 24) for blk in (256, 1024)
+            for gpc in (1, 8)]
+    cfgs += [sq.cfg(block=blk, grid_per_cu=1, xcd_map=2, tile_log2=tl) for tl in (10, 11, 12, 14)
+             for blk in (64, 128, 256)]
+    cfgs += [sq.cfg(block=blk, grid_per_cu=gpc, xcd_map=1, tile_log2=tl) for tl in (10, 12, 14, 16)
+             for blk in (64, 256, 1024) for gpc in (1, 4)]
+    for c in cfgs:
+        log(f"batch seed={seed} m={b.m} cfg={c.as_dict()}")
+        db.out.zero_()
+        sq.fill_batch(db, launch_cfg=c)
+        got = to_host_bytes(db.out)[: b.arena_bytes]
+        assert got.tobytes() == ref.tobytes(), (c.as_dict(), first_diff(got, ref))
+        assert sq.batch_errors(db) == 0
 
 
 def test_batch_equals_per_stream_fills(sq):

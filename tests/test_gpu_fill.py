@@ -58,15 +58,13 @@ def test_fill_every_config(sq, oracle_mod, kind):
     n = 3 * (1 << 18) + 7
     key, ctr0 = 0xE3B0C44298FC1C14, 2**64 - 100000
     ref = oracle_bytes(oracle_mod, kind, key, ctr0, n)
-    for block in (256, 512, 1024):
-        for unroll in (4, 8):
-            for gpc in (1, 4, 16, 64):
-                for xcd in (0, 1):
-                    c = sq.cfg(block, unroll, gpc, xcd)
-                    log(f"fill kind={kind} cfg={c.as_dict()} n={n}")
-                    out = sq.fill(kind, key, ctr0, n, launch_cfg=c)
-                    got = to_host_bytes(out)
-                    assert got.tobytes() == ref.tobytes(), (c.as_dict(), first_diff(got, ref))
+    cfgs = [sq.cfg(b, u, 1, 2) for b in (64, 128, 256, 512, 1024) for u in (1, 2, 4, 8)]
+    cfgs += [sq.cfg(b, u, g, x) for b in (64, 256, 1024) for u in (1, 4, 8) for g in (1, 4, 16, 64) for x in (0, 1)]
+    for c in cfgs:
+        log(f"fill kind={kind} cfg={c.as_dict()} n={n}")
+        out = sq.fill(kind, key, ctr0, n, launch_cfg=c)
+        got = to_host_bytes(out)
+        assert got.tobytes() == ref.tobytes(), (c.as_dict(), first_diff(got, ref))
 
 
 def test_invalid_arguments(sq):
@@ -90,7 +88,7 @@ def test_invalid_arguments(sq):
     assert e.value.status == -1
     sq.fill_ptr(0, 1, 0, 0, 0)  # n == 0: no launch, OK
     with pytest.raises(sq.SquaresError):
-        sq.fill(0, 1, 0, 16, launch_cfg=sq.cfg(block=128))
+        sq.fill(0, 1, 0, 16, launch_cfg=sq.cfg(block=96))
 
 
 def test_argument_order_matches_paper_scalar(sq, oracle_mod):
@@ -155,4 +153,34 @@ def test_full_size_sampled(sq, oracle_mod, kind):
     for row, i in zip(got, idx):
         assert row.tobytes() == oracle_element(oracle_mod, kind, c.key, c.ctr0, int(i)), f"position {int(i)}"
     del out, iv
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("kind", [0, 2])
+def test_full_size_complete(sq, oracle_mod, kind):
+    """Every one of the n = 2^32 squares32 (16 GiB) or squares64 (32 GiB)
+    outputs of the single-key workload, in the benchmark's launch
+    configuration, equals the oracle's: compared in chunks of 2^28 outputs,
+    the oracle running on all host threads into a reused buffer."""
+    import torch
+
+    from paper_2004_06278_amd import workloads as W
+
+    c = W.single_key_case()
+    n, chunk = 1 << 32, 1 << 28
+    log(f"full-size complete compare kind={kind} key={c.key:#x} ctr0={c.ctr0:#x} n={n}")
+    out = sq.fill(kind, c.key, c.ctr0, n)
+    tdt = torch.int32 if kind == 0 else torch.int64
+    ndt = np.uint32 if kind == 0 else np.uint64
+    flat = out.view(tdt)
+    host = torch.empty(chunk, dtype=tdt, pin_memory=True)
+    ref = np.empty(chunk, dtype=ndt)
+    for base in range(0, n, chunk):
+        host.copy_(flat[base: base + chunk])
+        oracle_mod.fill_into(kind, c.key, (c.ctr0 + base) % 2**64, ref, threads=HOST_THREADS)
+        got = host.numpy().view(ndt)
+        if not np.array_equal(got, ref):
+            bad = int(np.nonzero(got != ref)[0][0])
+            pytest.fail(f"first mismatch at output {base + bad}")
+    del out, flat
     torch.cuda.empty_cache()

@@ -64,14 +64,12 @@ def test_strided_fill_every_config(sq, oracle_mod, kind):
     n = (1 << 19) + 13
     key, ctr0, step = 0x3C6EF372FE94F82B, 2**64 - 77777, 0x10001
     ref = oracle_mod.fill_strided(kind, key, ctr0, step, n).view(np.uint8)
-    for block in (256, 1024):
-        for unroll in (4, 8):
-            for gpc in (1, 16):
-                for xcd in (0, 1):
-                    c = sq.cfg(block, unroll, gpc, xcd)
-                    log(f"strided kind={kind} cfg={c.as_dict()}")
-                    got = to_host_bytes(sq.fill_strided(kind, key, ctr0, step, n, launch_cfg=c))
-                    assert got.tobytes() == ref.tobytes(), (c.as_dict(), first_diff(got, ref))
+    cfgs = [sq.cfg(b, u, 1, 2) for b in (64, 256, 1024) for u in (1, 2, 4, 8)]
+    cfgs += [sq.cfg(b, u, g, x) for b in (256, 1024) for u in (4, 8) for g in (1, 16) for x in (0, 1)]
+    for c in cfgs:
+        log(f"strided kind={kind} cfg={c.as_dict()}")
+        got = to_host_bytes(sq.fill_strided(kind, key, ctr0, step, n, launch_cfg=c))
+        assert got.tobytes() == ref.tobytes(), (c.as_dict(), first_diff(got, ref))
 
 
 @pytest.mark.parametrize("kind", KINDS)
@@ -195,12 +193,12 @@ def test_key_counter_every_config(sq, oracle_mod, kind):
     keys = _keys(g, m)
     kd = torch.from_numpy(keys.view(np.int64)).cuda()
     ref = oracle_mod.fill_keys(kind, 0, keys).view(np.uint8)
-    for block in (256, 512, 1024):
-        for gpc in (1, 8, 64):
-            c = sq.cfg(block, 4, gpc)
-            log(f"keys kind={kind} cfg={c.as_dict()}")
-            got = to_host_bytes(sq.fill_keys(kind, 0, kd, launch_cfg=c))
-            assert got.tobytes() == ref.tobytes(), c.as_dict()
+    cfgs = [sq.cfg(b, 4, g) for b in (64, 256, 512, 1024) for g in (1, 8, 64)]
+    cfgs += [sq.cfg(b, 4, 1, 2) for b in (64, 128, 256, 1024)]
+    for c in cfgs:
+        log(f"keys kind={kind} cfg={c.as_dict()}")
+        got = to_host_bytes(sq.fill_keys(kind, 0, kd, launch_cfg=c))
+        assert got.tobytes() == ref.tobytes(), c.as_dict()
 
 
 def test_key_counter_equals_batch_of_single_outputs(sq):
