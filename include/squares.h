@@ -117,8 +117,8 @@ int sq_uniform_f32x2(uint64_t key, uint64_t ctr0, uint64_t n, float *out, void *
 typedef struct {
     uint32_t block;        /* threads per workgroup: 64, 128, 256, 512 or 1024 (fill);
                               256, 512 or 1024 (batch); reduce uses 256 */
-    uint32_t unroll;       /* 16-byte vectors per lane per chunk: 1, 2, 4 or 8 (fill);
-                              outputs per lane per step for reduce: 1, 2 or 4 */
+    uint32_t unroll;       /* 16-byte vectors per lane per chunk: 1, 2, 4 or 8 (fill and
+                              batch); outputs per lane per step for reduce: 1, 2 or 4 */
     uint32_t grid_per_cu;  /* workgroups per compute unit (grid = CUs * this), 1..64 */
     uint32_t xcd_map;      /* fill chunk order.  0: grid-stride, consecutive chunks
                               round-robin over the 8 XCDs; 1: grid-stride, each XCD

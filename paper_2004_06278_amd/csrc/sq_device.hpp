@@ -34,6 +34,13 @@ __device__ __forceinline__ uint64_t opaque(uint64_t v) {
   return v;
 }
 
+// The same for a workgroup-uniform value, kept in scalar registers: stops
+// LLVM from folding a uniform term back into a per-lane product.
+__device__ __forceinline__ uint64_t opaque_uniform(uint64_t v) {
+  asm volatile("" : "+s"(v));
+  return v;
+}
+
 // The two instruction groups of a round, each pinned with a non-volatile
 // asm statement so that LLVM can schedule them but not rewrite them (with
 // plain C it duplicates the multiply-add, strength-reduces round 1's y*y + y

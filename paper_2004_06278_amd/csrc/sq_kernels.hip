@@ -29,6 +29,7 @@ struct FillArgs {
   unsigned char* out;   // address of element 0 (element-aligned)
   uint64_t nvec;        // full 16-byte vectors in the aligned body
   uint64_t nchunks;     // ceil(nvec / (block * U))
+  uint64_t full_chunks; // floor(nvec / (block * U))
   uint64_t step;        // counter increment between consecutive outputs
   uint64_t dkey;        // step * key: first-Weyl-term increment per counter visited
   uint64_t y_body;      // first Weyl term of the body: (ctr0 + step * counter offset of head) * key
@@ -51,6 +52,13 @@ __device__ __forceinline__ void fill_edges(const FillArgs& a) {
   }
 }
 
+// c < n for workgroup-uniform values using 32-bit compares, which stay on
+// the scalar unit (gfx950 has no 64-bit scalar less-than).
+__device__ __forceinline__ bool uniform_lt(uint64_t c, uint64_t n) {
+  const uint32_t ch = (uint32_t)(c >> 32), nh = (uint32_t)(n >> 32);
+  return ch < nh || (ch == nh && (uint32_t)c < (uint32_t)n);
+}
+
 // One 16-byte vector of the body: unit counter increments share each
 // counter's second Weyl term with the next counter's first.
 template <int K, bool S>
@@ -67,13 +75,17 @@ __device__ __forceinline__ void fill_chunk(const FillArgs& a, uint64_t c) {
   constexpr int W = Kind<K>::W;
   const uint32_t B = blockDim.x, tid = threadIdx.x;
   unsigned char* body = a.out + (uint64_t)a.head * W;
-  const uint64_t v0 = c * B * U + tid;
+  // The chunk's first vector and its Weyl term are workgroup-uniform (scalar
+  // registers); each lane adds only its own 32-bit offset.
+  const uint64_t c0 = c * B * U;
+  const uint64_t yc = opaque_uniform(a.y_body + c0 * a.ekey);
+  const uint64_t v0 = c0 + tid;
   // opaque: otherwise loop-strength reduction keeps a separate induction
   // variable (two VGPRs each) for every unrolled vector's y
-  uint64_t y = opaque(a.y_body + v0 * a.ekey);
+  uint64_t y = opaque(yc + (uint64_t)tid * a.ekey);
   const uint64_t step = (uint64_t)B * a.ekey;
-  u32x4* p = (u32x4*)(body + v0 * 16);
-  if ((c + 1) * B * U <= a.nvec) {
+  u32x4* p = (u32x4*)body + c0 + tid;
+  if (uniform_lt(c, a.full_chunks)) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       p[(uint64_t)u * B] = body_vec<K, S>(a, y);
@@ -99,7 +111,7 @@ __global__ __launch_bounds__(1024) void k_fill(FillArgs a) {
     // one chunk per workgroup (grid = nchunks): workgroups retire and the
     // next ones start in dispatch order, so the chip writes one narrow
     // moving window of the output
-    if (blockIdx.x < a.nchunks) fill_chunk<K, U, S>(a, blockIdx.x);
+    if (blockIdx.x < (uint32_t)a.nchunks) fill_chunk<K, U, S>(a, blockIdx.x);  // nchunks < 2^31 here
   } else if (a.xcd_map == 0) {
 #pragma unroll 1
     for (uint64_t c = blockIdx.x; c < a.nchunks; c += gridDim.x) fill_chunk<K, U, S>(a, c);
@@ -391,9 +403,9 @@ __global__ __launch_bounds__(256) void k_batch_map(const sqi::BatchHdr* hdr, con
 // (element-aligned): a head up to the next 1 KiB boundary and a tail,
 // element stores, and in between chunks of B*8 16-byte vectors laid out as
 // in the plain fill (each store instruction of a wave covers one aligned KiB).
-template <int K>
+template <int K, int U>
 __device__ __forceinline__ void fill_range(uint64_t key, uint64_t ctr, uint64_t cnt, unsigned char* p) {
-  constexpr int W = Kind<K>::W, E = 16 / W, U = 8;
+  constexpr int W = Kind<K>::W, E = 16 / W;
   const uint32_t tid = threadIdx.x, B = blockDim.x;
   const uint32_t mis = (uint32_t)((uintptr_t)p & 1023u);
   uint64_t head = mis ? (1024u - mis) / W : 0;
@@ -433,6 +445,7 @@ __device__ __forceinline__ void fill_range(uint64_t key, uint64_t ctr, uint64_t 
 }
 
 // One tile: the stream is one load from the tile map.
+template <int U>
 __device__ __forceinline__ void batch_tile(const sqi::BatchDesc& d, uint32_t lg, const uint64_t* ts,
                                            const uint32_t* map, uint64_t t) {
   const uint64_t T = 1ull << lg;
@@ -445,12 +458,12 @@ __device__ __forceinline__ void batch_tile(const sqi::BatchDesc& d, uint32_t lg,
   const uint64_t key = d.keys[s], ctr = d.ctr0s[s] + (split ? off >> 1 : off);
   unsigned char* p = d.out + d.offs[s] + off * ((kind == 2 || kind == 3) ? 8u : 4u);
   switch (kind) {
-    case 0: fill_range<0>(key, ctr, cnt, p); break;
-    case 1: fill_range<1>(key, ctr, cnt, p); break;
-    case 2: fill_range<2>(key, ctr, cnt, p); break;
-    case 3: fill_range<3>(key, ctr, cnt, p); break;
-    case 4: fill_range<4>(key, ctr, cnt, p); break;
-    default: fill_range<5>(key, ctr, cnt, p); break;
+    case 0: fill_range<0, U>(key, ctr, cnt, p); break;
+    case 1: fill_range<1, U>(key, ctr, cnt, p); break;
+    case 2: fill_range<2, U>(key, ctr, cnt, p); break;
+    case 3: fill_range<3, U>(key, ctr, cnt, p); break;
+    case 4: fill_range<4, U>(key, ctr, cnt, p); break;
+    default: fill_range<5, U>(key, ctr, cnt, p); break;
   }
 }
 
@@ -460,12 +473,13 @@ __device__ __forceinline__ void batch_tile(const sqi::BatchDesc& d, uint32_t lg,
 // order 1: a persistent grid takes tiles from a queue in tile order, so
 // workgroups that finish early take more (the write front stays narrow and
 // no workgroup idles while another still has a static share left).
+template <int U>
 __global__ __launch_bounds__(1024) void k_batch_fill(sqi::BatchDesc d, uint32_t lg, uint32_t order,
                                                      sqi::BatchHdr* hdr, const uint64_t* ts, const uint32_t* map) {
   const uint64_t total = hdr->total_tiles;
   if (order != 1) {
 #pragma unroll 1
-    for (uint64_t t = blockIdx.x; t < total; t += gridDim.x) batch_tile(d, lg, ts, map, t);
+    for (uint64_t t = blockIdx.x; t < total; t += gridDim.x) batch_tile<U>(d, lg, ts, map, t);
     return;
   }
   __shared__ uint64_t s_tile;
@@ -476,7 +490,7 @@ __global__ __launch_bounds__(1024) void k_batch_fill(sqi::BatchDesc d, uint32_t 
     const uint64_t t = s_tile;
     __syncthreads();  // every lane has read s_tile before lane 0 overwrites it
     if (t >= total) break;
-    batch_tile(d, lg, ts, map, t);
+    batch_tile<U>(d, lg, ts, map, t);
   }
 }
 
@@ -671,6 +685,7 @@ hipError_t launch_fill(int kind, uint64_t key, uint64_t ctr0, uint64_t n, void* 
   a.tail = (uint32_t)(n - head - a.nvec * E);
   const uint64_t per_chunk = (uint64_t)cfg.block * cfg.unroll;
   a.nchunks = (a.nvec + per_chunk - 1) / per_chunk;
+  a.full_chunks = a.nvec / per_chunk;
   const bool split = kind == SQ_U32X2 || kind == SQ_F32X2;  // head is even: out is 8-byte aligned
   a.step = step;
   a.dkey = step * key;
@@ -800,7 +815,9 @@ static hipError_t launch_batch_body(const BatchDesc& d, const uint32_t* m_dev, v
   // takes tiles in a static interleave (0) or from the queue (1)
   const uint32_t grid = cfg.xcd_map == 2 ? (uint32_t)std::min<uint64_t>(max_tiles, 0x7FFFFFFFull)
                                          : (uint32_t)device_info().cus * cfg.grid_per_cu;
-  hipLaunchKernelGGL(k_batch_fill, dim3(grid), dim3(cfg.block), 0, s, d, cfg.tile_log2, cfg.xcd_map, hdr,
+  auto k = cfg.unroll == 1 ? k_batch_fill<1> : cfg.unroll == 2 ? k_batch_fill<2>
+          : cfg.unroll == 4 ? k_batch_fill<4> : k_batch_fill<8>;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(cfg.block), 0, s, d, cfg.tile_log2, cfg.xcd_map, hdr,
                      (const uint64_t*)ts, (const uint32_t*)map);
   return hipGetLastError();
 }

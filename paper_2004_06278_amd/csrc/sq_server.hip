@@ -338,7 +338,7 @@ int sq_server_create(const sq_server_cfg* cfg, sq_server** out) {
   // Ticks are many small batches over a large arena: a persistent grid with
   // the static tile interleave (no tile-bound grid, no queue) and 2^14-output
   // tiles gave the lowest latency in open-loop runs on MI355X.
-  s->lcfg = sq_launch_cfg{256, 1, 4, 0, 14};
+  s->lcfg = sq_launch_cfg{256, 8, 4, 0, 14};
   if (cfg->tile_log2) s->lcfg.tile_log2 = cfg->tile_log2;
   s->arena = new Arena(cfg->hbm_budget_bytes);
   hipError_t e = hipMalloc((void**)&s->arena_dev, cfg->hbm_budget_bytes);

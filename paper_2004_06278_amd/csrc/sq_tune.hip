@@ -51,7 +51,8 @@ bool cfg_valid(sq_op op, const sq_launch_cfg& c) {
     case SQ_OP_REDUCE:
       return in(c.unroll, {1, 2, 4});
     case SQ_OP_BATCH:
-      return in(c.block, {64, 128, 256, 512, 1024}) && c.tile_log2 >= 10 && c.tile_log2 <= 24 && c.xcd_map <= 2;
+      return in(c.block, {64, 128, 256, 512, 1024}) && in(c.unroll, {1, 2, 4, 8}) && c.tile_log2 >= 10 &&
+             c.tile_log2 <= 24 && c.xcd_map <= 2;
   }
   return false;
 }
@@ -70,7 +71,7 @@ sq_launch_cfg default_cfg(sq_op op, int kind, uint64_t n) {
     // a persistent grid of two 256-lane workgroups per CU taking tiles of
     // 2^16 outputs from the queue: the fastest ragged-batch shape measured
     // on MI355X (dynamic balance with few descriptor loads per byte)
-    default: return sq_launch_cfg{256, 1, 2, 1, 16};
+    default: return sq_launch_cfg{256, 8, 2, 1, 16};
   }
 }
 
@@ -414,13 +415,14 @@ int sq_autotune(uint32_t op_mask, uint64_t max_bytes, const char* save_path) {
       // grids with larger ones
       std::vector<sq_launch_cfg> cands;
       for (uint32_t tl : {10u, 11u, 12u, 13u})
-        for (uint32_t blk : {64u, 128u, 256u}) cands.push_back(sq_launch_cfg{blk, 1, 1, 2, tl});
+        for (uint32_t blk : {64u, 128u, 256u}) cands.push_back(sq_launch_cfg{blk, 8, 1, 2, tl});
       for (uint32_t tl : {14u, 16u, 18u})
         for (uint32_t blk : {256u, 1024u})
-          for (uint32_t g : {2u, 4u, 8u, 16u}) cands.push_back(sq_launch_cfg{blk, 1, g, 0, tl});
-      for (uint32_t tl : {13u, 14u, 15u, 16u, 17u, 18u})
-        for (uint32_t blk : {256u, 512u})
-          for (uint32_t g : {1u, 2u, 4u}) cands.push_back(sq_launch_cfg{blk, 1, g, 1, tl});
+          for (uint32_t g : {2u, 4u, 8u, 16u}) cands.push_back(sq_launch_cfg{blk, 8, g, 0, tl});
+      for (uint32_t tl : {14u, 15u, 16u, 17u, 18u})
+        for (uint32_t blk : {64u, 256u, 512u})
+          for (uint32_t g : {2u, 4u})
+            for (uint32_t u : {2u, 8u}) cands.push_back(sq_launch_cfg{blk, u, g, 1, tl});
       for (const sq_launch_cfg& c : cands) {
         if (e != hipSuccess) break;
         const sq_launch_cfg inc = best_c;

@@ -37,6 +37,8 @@ def test_batch_small_random(sq, oracle_mod, seed):
              for blk in (64, 128, 256)]
     cfgs += [sq.cfg(block=blk, grid_per_cu=gpc, xcd_map=1, tile_log2=tl) for tl in (10, 12, 14, 16)
              for blk in (64, 256, 1024) for gpc in (1, 4)]
+    cfgs += [sq.cfg(block=blk, unroll=u, grid_per_cu=2, xcd_map=o, tile_log2=tl) for u in (1, 2, 4)
+             for o in (0, 1) for tl in (11, 15) for blk in (64, 256)]
     for c in cfgs:
         log(f"batch seed={seed} m={b.m} cfg={c.as_dict()}")
         db.out.zero_()
