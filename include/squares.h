@@ -123,7 +123,10 @@ typedef struct {
     uint32_t xcd_map;      /* fill chunk order.  0: grid-stride, consecutive chunks
                               round-robin over the 8 XCDs; 1: grid-stride, each XCD
                               takes one contiguous eighth of the range; 2: one chunk
-                              per workgroup (grid = chunks, grid_per_cu unused) */
+                              per workgroup (grid = chunks, grid_per_cu unused).
+                              reduce: 0 static split over a resident grid; 1 the
+                              resident grid takes chunks of 256 * 2^tile_log2
+                              counters (tile_log2 6..16) from a queue */
     uint32_t tile_log2;    /* batch only: outputs per tile = 2^tile_log2, 10..24
                               (batch xcd_map: 0 persistent grid, static interleave;
                               1 persistent grid, tiles taken from a queue in order;
@@ -160,13 +163,16 @@ int sq_autotune(uint32_t op_mask, uint64_t max_bytes, const char *save_path);
  *   SQ_U32: squares32        SQ_F32: squares32 >> 8   (value = sum * 2^-24)
  *   SQ_U64: squares64        SQ_F64: squares64 >> 11  (value = sum * 2^-53)
  *   SQ_U32X2: each word      SQ_F32X2: each word >> 8 (value = sum * 2^-24)
- * over the same n outputs a fill of that kind would write.
- * as an exact 128-bit integer, so the result does not depend on the order of
- * summation or on the launch configuration.  `value` is that sum times the
- * kind's scale rounded to the nearest double (ties to even).
+ * over the same n outputs a fill of that kind would write, as an exact
+ * 128-bit integer, so the result does not depend on the order of summation
+ * or on the launch configuration.  `value` is that sum times the kind's
+ * scale rounded to the nearest double (ties to even).
  * `out` is a DEVICE pointer to one sq_sum_result.  `ws` is a device
  * workspace of at least sq_reduce_workspace_bytes(n) bytes (16-byte
- * aligned), else SQ_ENOMEM.  n == 0 writes a zero result.
+ * aligned), else SQ_ENOMEM: per-workgroup 128-bit partials and the chunk
+ * queue counter, which the call resets itself (no caller initialisation;
+ * calls that share one workspace must be ordered on one stream).
+ * n == 0 writes a zero result.
  * ------------------------------------------------------------------------ */
 typedef struct {
     uint64_t lo;     /* low 64 bits of the exact integer sum */

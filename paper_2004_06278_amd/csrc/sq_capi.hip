@@ -235,7 +235,7 @@ int sq_make_keys(uint64_t gen_key, uint64_t ctr0, uint64_t m, uint64_t* keys, vo
 // ---------------------------------------------------------------- reduce
 size_t sq_reduce_workspace_bytes(uint64_t n) {
   (void)n;
-  return 16ull * kReduceMaxParts;
+  return 16ull * kReduceMaxParts + 256;  // 128-bit partials, then the chunk queue counter
 }
 
 int sq_reduce_strided_cfg(sq_kind kind, uint64_t key, uint64_t ctr0, uint64_t step, uint64_t n,

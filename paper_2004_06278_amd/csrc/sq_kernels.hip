@@ -158,8 +158,10 @@ struct ReduceArgs {
   uint64_t y0;           // (ctr0 + per * step * thread) * key is y0 + thread * ythread
   uint64_t ythread;      // per * dkey
   uint64_t n;            // counters to sum (split kinds: pairs of outputs)
-  uint64_t per;          // counters per thread (contiguous)
+  uint64_t per;          // counters per thread (contiguous; per chunk in queue order)
   uint64_t* partials;    // 2 x u64 per workgroup
+  unsigned long long* next;  // queue order: next chunk
+  uint64_t nchunks;          // queue order: chunks of blockDim.x * per counters
 };
 
 // Advances the first Weyl term past the counter whose second term is z: by
@@ -201,17 +203,11 @@ __device__ __forceinline__ void block_sum128(uint64_t& lo, uint64_t& hi) {
 // Each thread sums its own contiguous run of counters.  The integer terms
 // are accumulated exactly: in 64 bits over runs short enough not to
 // overflow (FLUSH terms), then into a 128-bit total.
+// Adds the integer terms of cnt consecutive counters, the first with Weyl
+// term y, to the 128-bit (lo, hi).
 template <int K, int U, bool S>
-__global__ __launch_bounds__(256) void k_reduce(ReduceArgs a) {
-  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  uint64_t cnt = 0;
-  if (__umul64hi(t, a.per) == 0 && t * a.per < a.n) {
-    const uint64_t begin = t * a.per;
-    cnt = a.n - begin < a.per ? a.n - begin : a.per;
-  }
-  const uint64_t key = a.key, dkey = a.dkey;
-  uint64_t y = a.y0 + t * a.ythread;
-  uint64_t lo = 0, hi = 0;
+__device__ __forceinline__ void run_sum(uint64_t y, uint64_t cnt, uint64_t key, uint64_t dkey, uint64_t& lo,
+                                        uint64_t& hi) {
   if constexpr (K == 2) {
     // 64-bit terms: a 64-bit partial plus a 32-bit count of its carries,
     // folded into the 128-bit total every 2^20 terms
@@ -275,11 +271,56 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a) {
       i += len;
     }
   }
+}
+
+// Static order: thread t sums counters [t*per, (t+1)*per) of the range.
+template <int K, int U, bool S>
+__global__ __launch_bounds__(256) void k_reduce(ReduceArgs a) {
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t cnt = 0;
+  if (__umul64hi(t, a.per) == 0 && t * a.per < a.n) {
+    const uint64_t begin = t * a.per;
+    cnt = a.n - begin < a.per ? a.n - begin : a.per;
+  }
+  uint64_t lo = 0, hi = 0;
+  run_sum<K, U, S>(a.y0 + t * a.ythread, cnt, a.key, a.dkey, lo, hi);
   block_sum128(lo, hi);
   if (threadIdx.x == 0) {
     a.partials[2 * blockIdx.x] = lo;
     a.partials[2 * blockIdx.x + 1] = hi;
   }
+}
+
+// Queue order: a resident grid takes chunks of blockDim.x * per counters
+// from a counter in the workspace (zeroed by k_reduce_reset just before), so
+// workgroups that run faster take more chunks; thread t of chunk c sums
+// counters [c*B*per + t*per, +per).  Exact integer sums, so the result does
+// not depend on which workgroup took which chunk.
+template <int K, int U, bool S>
+__global__ __launch_bounds__(256) void k_reduce_queue(ReduceArgs a) {
+  __shared__ uint64_t s_chunk;
+  const uint64_t chunk = (uint64_t)blockDim.x * a.per;
+  uint64_t lo = 0, hi = 0;
+#pragma unroll 1
+  while (true) {
+    if (threadIdx.x == 0) s_chunk = atomicAdd(a.next, 1ull);
+    __syncthreads();
+    const uint64_t c = s_chunk;
+    __syncthreads();  // every lane has read s_chunk before lane 0 overwrites it
+    if (c >= a.nchunks) break;
+    const uint64_t begin = c * chunk + (uint64_t)threadIdx.x * a.per;
+    const uint64_t cnt = begin < a.n ? (a.n - begin < a.per ? a.n - begin : a.per) : 0;
+    run_sum<K, U, S>(a.y0 + begin * a.dkey, cnt, a.key, a.dkey, lo, hi);
+  }
+  block_sum128(lo, hi);
+  if (threadIdx.x == 0) {
+    a.partials[2 * blockIdx.x] = lo;
+    a.partials[2 * blockIdx.x + 1] = hi;
+  }
+}
+
+__global__ void k_reduce_reset(unsigned long long* next) {
+  if (threadIdx.x == 0) *next = 0;
 }
 
 // Sums the workgroup partials.  For a split kind with an odd count, the
@@ -302,24 +343,24 @@ __global__ __launch_bounds__(256) void k_reduce_final(const uint64_t* partials, 
 }
 
 typedef void (*ReduceKernel)(ReduceArgs);
-template <int K, bool S>
+template <int K, bool S, bool Q>
 ReduceKernel reduce_kernel_for(uint32_t unroll) {
   switch (unroll) {
-    case 1: return k_reduce<K, 1, S>;
-    case 2: return k_reduce<K, 2, S>;
-    default: return k_reduce<K, 4, S>;
+    case 1: return Q ? k_reduce_queue<K, 1, S> : k_reduce<K, 1, S>;
+    case 2: return Q ? k_reduce_queue<K, 2, S> : k_reduce<K, 2, S>;
+    default: return Q ? k_reduce_queue<K, 4, S> : k_reduce<K, 4, S>;
   }
 }
 
-template <bool S>
+template <bool S, bool Q>
 ReduceKernel reduce_kernel(int kind, uint32_t unroll) {
   switch (kind) {
-    case SQ_U32: return reduce_kernel_for<0, S>(unroll);
-    case SQ_F32: return reduce_kernel_for<1, S>(unroll);
-    case SQ_U64: return reduce_kernel_for<2, S>(unroll);
-    case SQ_F64: return reduce_kernel_for<3, S>(unroll);
-    case SQ_U32X2: return reduce_kernel_for<4, S>(unroll);
-    default: return reduce_kernel_for<5, S>(unroll);
+    case SQ_U32: return reduce_kernel_for<0, S, Q>(unroll);
+    case SQ_F32: return reduce_kernel_for<1, S, Q>(unroll);
+    case SQ_U64: return reduce_kernel_for<2, S, Q>(unroll);
+    case SQ_F64: return reduce_kernel_for<3, S, Q>(unroll);
+    case SQ_U32X2: return reduce_kernel_for<4, S, Q>(unroll);
+    default: return reduce_kernel_for<5, S, Q>(unroll);
   }
 }
 
@@ -754,7 +795,11 @@ static int resident_blocks(const void* k, uint32_t block) {
 hipError_t launch_reduce(int kind, uint64_t key, uint64_t ctr0, uint64_t n, sq_sum_result* out, void* ws,
                          const sq_launch_cfg& cfg, hipStream_t s, uint64_t step) {
   const uint32_t B = 256;  // reduce workgroups are 256 threads (block_sum128 LDS sized for <= 1024)
-  ReduceKernel k = step == 1 ? reduce_kernel<false>(kind, cfg.unroll) : reduce_kernel<true>(kind, cfg.unroll);
+  const bool queue = cfg.xcd_map == 1;
+  ReduceKernel k = step == 1 ? (queue ? reduce_kernel<false, true>(kind, cfg.unroll)
+                                      : reduce_kernel<false, false>(kind, cfg.unroll))
+                             : (queue ? reduce_kernel<true, true>(kind, cfg.unroll)
+                                      : reduce_kernel<true, false>(kind, cfg.unroll));
   const bool split = kind == SQ_U32X2 || kind == SQ_F32X2;
   const uint64_t units = split ? n / 2 : n;  // counters with all their outputs summed
   // Every thread gets the same amount of work, so the grid must be resident
@@ -773,8 +818,20 @@ hipError_t launch_reduce(int kind, uint64_t key, uint64_t ctr0, uint64_t n, sq_s
   a.per = units / T + (units % T != 0);
   a.dkey = step * key;
   a.y0 = ctr0 * key;
-  a.ythread = a.per * a.dkey;
   a.partials = (uint64_t*)ws;
+  if (queue) {
+    // chunks of B * 2^tile_log2 counters, taken from the queue counter that
+    // follows the partials in the workspace
+    a.per = 1ull << cfg.tile_log2;
+    const uint64_t chunk = (uint64_t)B * a.per;
+    a.nchunks = units / chunk + (units % chunk != 0);
+    if (grid > a.nchunks) grid = a.nchunks ? a.nchunks : 1;
+    a.next = (unsigned long long*)((unsigned char*)ws + 16ull * kReduceMaxParts);
+    hipLaunchKernelGGL(k_reduce_reset, dim3(1), dim3(64), 0, s, a.next);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  a.ythread = a.per * a.dkey;
   hipLaunchKernelGGL(k, dim3((uint32_t)grid), dim3(B), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

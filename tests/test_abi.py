@@ -99,6 +99,9 @@ def test_reduce_argument_checks():
     assert _rc(L.sq_reduce_cfg, 1, 1, 0, 10, FAKE, FAKE + 8, need, good, None)[0] == -2
     assert _rc(L.sq_reduce_cfg, 1, 1, 0, 10, FAKE, FAKE, need - 16, good, None)[0] == -3
     assert _rc(L.sq_reduce_cfg, 1, 1, 0, 10, FAKE, FAKE, need, squares.LaunchCfg(256, 3, 8, 0, 16), None)[0] == -1
+    # queue order: per-thread chunk 2^6..2^16 counters; no order 2 for reduce
+    assert _rc(L.sq_reduce_cfg, 1, 1, 0, 10, FAKE, FAKE, need, squares.LaunchCfg(256, 4, 8, 1, 5), None)[0] == -1
+    assert _rc(L.sq_reduce_cfg, 1, 1, 0, 10, FAKE, FAKE, need, squares.LaunchCfg(256, 4, 8, 2, 16), None)[0] == -1
 
 
 def test_mode_argument_checks():

@@ -40,12 +40,31 @@ def test_reduce_every_config(sq, oracle_mod, kind):
     n = (1 << 21) + 77
     key, ctr0 = 0x51A8F3C2E9D07B64, 2**64 - 12345
     ref = oracle_mod.exact_sum(kind, key, ctr0, n, threads=HOST_THREADS)
-    for unroll in (1, 2, 4):
-        for gpc in (1, 2, 8, 32, 64):
-            c = sq.cfg(256, unroll, gpc)
-            log(f"reduce kind={kind} cfg={c.as_dict()}")
-            s, v, _ = sq.reduce(kind, key, ctr0, n, launch_cfg=c)
-            assert s == ref, c.as_dict()
+    cfgs = [sq.cfg(256, u, g) for u in (1, 2, 4) for g in (1, 2, 8, 32, 64)]
+    cfgs += [sq.cfg(256, u, g, 1, pl) for u in (1, 4) for g in (1, 8, 64) for pl in (6, 9, 12, 16)]
+    for c in cfgs:
+        log(f"reduce kind={kind} cfg={c.as_dict()}")
+        s, v, _ = sq.reduce(kind, key, ctr0, n, launch_cfg=c)
+        assert s == ref, c.as_dict()
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_reduce_queue_order_small_and_ragged(sq, oracle_mod, kind):
+    """The chunk-queue order (a resident grid taking chunks from a counter in
+    the workspace) on sizes from 0 to a few chunks plus a ragged tail, twice
+    in a row on the same workspace (the counter is reset by each call)."""
+    g = np.random.Generator(np.random.PCG64(300 + kind))
+    res, ws = sq.result_tensor(), sq.reduce_workspace()
+    for n in (0, 1, 2, 3, 255, 256 * 64 - 1, 256 * 64 + 1, 1000003):
+        key = int(g.integers(0, 2**64, dtype=np.uint64))
+        ctr0 = 2**64 - int(g.integers(1, 1 << 20))
+        ref = oracle_mod.exact_sum(kind, key, ctr0, n, threads=HOST_THREADS)
+        for rep in range(2):
+            c = sq.cfg(256, 4, 4, 1, 6)
+            log(f"reduce queue kind={kind} n={n} rep={rep}")
+            sq.reduce_async(kind, key, ctr0, n, res, ws, launch_cfg=c)
+            s, v, nn = sq.read_result(res)
+            assert s == ref and nn == n and v == oracle_mod.rounded_value(kind, ref)
 
 
 @pytest.mark.parametrize("kind", KINDS)
