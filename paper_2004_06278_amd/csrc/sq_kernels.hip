@@ -444,10 +444,11 @@ __global__ __launch_bounds__(256) void k_batch_map(const sqi::BatchHdr* hdr, con
 // (element-aligned): a head up to the next 1 KiB boundary and a tail,
 // element stores, and in between chunks of B*8 16-byte vectors laid out as
 // in the plain fill (each store instruction of a wave covers one aligned KiB).
+// Lanes 0..B-1 of the workgroup take part.
 template <int K, int U>
-__device__ __forceinline__ void fill_range(uint64_t key, uint64_t ctr, uint64_t cnt, unsigned char* p) {
+__device__ __forceinline__ void fill_range(uint64_t key, uint64_t ctr, uint64_t cnt, unsigned char* p, uint32_t B) {
   constexpr int W = Kind<K>::W, E = 16 / W;
-  const uint32_t tid = threadIdx.x, B = blockDim.x;
+  const uint32_t tid = threadIdx.x;
   const uint32_t mis = (uint32_t)((uintptr_t)p & 1023u);
   uint64_t head = mis ? (1024u - mis) / W : 0;
   if (head > cnt) head = cnt;
@@ -485,27 +486,50 @@ __device__ __forceinline__ void fill_range(uint64_t key, uint64_t ctr, uint64_t 
   }
 }
 
-// One tile: the stream is one load from the tile map.
-template <int U>
-__device__ __forceinline__ void batch_tile(const sqi::BatchDesc& d, uint32_t lg, const uint64_t* ts,
-                                           const uint32_t* map, uint64_t t) {
+// Where tile t writes: its stream is one load from the tile map.
+struct TileDesc {
+  uint64_t t;
+  uint64_t key;
+  uint64_t ctr;
+  uint64_t cnt;
+  unsigned char* p;
+  uint32_t kind;
+  uint32_t pad;
+};
+
+__device__ __forceinline__ TileDesc tile_desc(const sqi::BatchDesc& d, uint32_t lg, const uint64_t* ts,
+                                              const uint32_t* map, uint64_t t) {
+  TileDesc r;
+  r.t = t;
   const uint64_t T = 1ull << lg;
   const uint32_t s = map[t];
   const uint64_t off = (t - ts[s]) << lg;
   const uint64_t len = d.lens[s];
-  const uint64_t cnt = len - off < T ? len - off : T;
-  const uint32_t kind = d.kinds[s];
-  const bool split = kind > 3;  // two elements per counter; tiles hold an even count
-  const uint64_t key = d.keys[s], ctr = d.ctr0s[s] + (split ? off >> 1 : off);
-  unsigned char* p = d.out + d.offs[s] + off * ((kind == 2 || kind == 3) ? 8u : 4u);
-  switch (kind) {
-    case 0: fill_range<0, U>(key, ctr, cnt, p); break;
-    case 1: fill_range<1, U>(key, ctr, cnt, p); break;
-    case 2: fill_range<2, U>(key, ctr, cnt, p); break;
-    case 3: fill_range<3, U>(key, ctr, cnt, p); break;
-    case 4: fill_range<4, U>(key, ctr, cnt, p); break;
-    default: fill_range<5, U>(key, ctr, cnt, p); break;
+  r.cnt = len - off < T ? len - off : T;
+  r.kind = d.kinds[s];
+  const bool split = r.kind > 3;  // two elements per counter; tiles hold an even count
+  r.key = d.keys[s];
+  r.ctr = d.ctr0s[s] + (split ? off >> 1 : off);
+  r.p = d.out + d.offs[s] + off * ((r.kind == 2 || r.kind == 3) ? 8u : 4u);
+  return r;
+}
+
+template <int U>
+__device__ __forceinline__ void run_tile(const TileDesc& r, uint32_t B) {
+  switch (r.kind) {
+    case 0: fill_range<0, U>(r.key, r.ctr, r.cnt, r.p, B); break;
+    case 1: fill_range<1, U>(r.key, r.ctr, r.cnt, r.p, B); break;
+    case 2: fill_range<2, U>(r.key, r.ctr, r.cnt, r.p, B); break;
+    case 3: fill_range<3, U>(r.key, r.ctr, r.cnt, r.p, B); break;
+    case 4: fill_range<4, U>(r.key, r.ctr, r.cnt, r.p, B); break;
+    default: fill_range<5, U>(r.key, r.ctr, r.cnt, r.p, B); break;
   }
+}
+
+template <int U>
+__device__ __forceinline__ void batch_tile(const sqi::BatchDesc& d, uint32_t lg, const uint64_t* ts,
+                                           const uint32_t* map, uint64_t t) {
+  run_tile<U>(tile_desc(d, lg, ts, map, t), blockDim.x);
 }
 
 // order 0: workgroup g takes tiles g, g + grid, g + 2*grid, ..., so the
@@ -867,10 +891,13 @@ static hipError_t launch_batch_body(const BatchDesc& d, const uint32_t* m_dev, v
                      (const uint64_t*)ts, map);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  // xcd_map 2: one tile per workgroup, grid = the tile bound (workgroups
-  // past the scanned total exit at once); otherwise a persistent grid that
-  // takes tiles in a static interleave (0) or from the queue (1)
-  const uint32_t grid = cfg.xcd_map == 2 ? (uint32_t)std::min<uint64_t>(max_tiles, 0x7FFFFFFFull)
+  // xcd_map 2: one tile per workgroup, grid = the bound on tiles of this
+  // size (each stream has at most len / 2^lg + 1 of them, and the streams'
+  // outputs of at least 4 bytes fit the arena); workgroups past the scanned
+  // total exit at once.  Otherwise a persistent grid that takes tiles in a
+  // static interleave (0) or from the queue (1).
+  const uint64_t tiles_bound = std::min<uint64_t>(max_tiles, (uint64_t)d.m + (d.out_bytes >> (cfg.tile_log2 + 2)) + 1);
+  const uint32_t grid = cfg.xcd_map == 2 ? (uint32_t)std::min<uint64_t>(tiles_bound, 0x7FFFFFFFull)
                                          : (uint32_t)device_info().cus * cfg.grid_per_cu;
   auto k = cfg.unroll == 1 ? k_batch_fill<1> : cfg.unroll == 2 ? k_batch_fill<2>
           : cfg.unroll == 4 ? k_batch_fill<4> : k_batch_fill<8>;
