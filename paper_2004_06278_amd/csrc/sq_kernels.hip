@@ -1,12 +1,15 @@
-// gfx950 kernels of the Squares RNG: bulk fill, fused exact reduce, ragged
-// batch (tile scan + persistent fill) and the serving tick expansion.
+// gfx950 kernels of the Squares RNG: bulk fill (unit and other counter
+// increments), fused exact reduce, ragged batch (tile scan, tile map and a
+// tile-queue fill), key-counter mode, key generation and the serving tick
+// expansion.
 //
 // Every kernel is plain VALU integer code (no MFMA: nothing is a
 // contraction).  Fills are bound by HBM write bandwidth: each lane produces
 // 16 bytes (four 32-bit or two 64-bit outputs of consecutive counters) per
 // global_store_dwordx4, so a wave writes 1 KiB contiguous per instruction,
-// and a workgroup writes `block * unroll` such vectors per chunk.  The
-// reduce writes nothing per element; it is bound by the VALU issue rate.
+// and a workgroup writes `block * unroll` such vectors per chunk (the
+// fastest launch gives each workgroup one 4 KiB chunk).  The reduce writes
+// nothing per element; it is bound by the VALU issue rate.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
