@@ -127,7 +127,9 @@ typedef struct {
                               reduce: 0 static split over a resident grid; 1 the
                               resident grid takes chunks of 256 * 2^tile_log2
                               counters (tile_log2 6..16) from a queue */
-    uint32_t tile_log2;    /* batch only: outputs per tile = 2^tile_log2, 10..24
+    uint32_t tile_log2;    /* batch only: a tile holds 2^tile_log2 * 4 bytes of output
+                              (2^tile_log2 outputs of 4-byte kinds, half as many of
+                              8-byte kinds), 10..24
                               (batch xcd_map: 0 persistent grid, static interleave;
                               1 persistent grid, tiles taken from a queue in order;
                               2 one tile per workgroup) */
@@ -264,8 +266,9 @@ int sq_make_keys(uint64_t gen_key, uint64_t ctr0, uint64_t m, uint64_t *keys, vo
  * reads that count.
  * `ws` needs sq_batch_workspace_bytes(m, out_bytes) bytes (16-byte aligned):
  * a header, the tile scan and a tile-to-stream map sized for the arena.
- * The work is split into tiles of 2^tile_log2 outputs; a tile scan and one
- * persistent kernel run on `stream`.
+ * The work is split into tiles of 2^tile_log2 * 4 bytes of output (the
+ * configuration's tile_log2); a tile scan, a tile map and one fill kernel
+ * run on `stream`.
  * ------------------------------------------------------------------------ */
 size_t sq_batch_workspace_bytes(uint32_t m, uint64_t out_bytes);
 int sq_fill_batch(const uint64_t *keys, const uint64_t *ctr0s, const uint64_t *lens,

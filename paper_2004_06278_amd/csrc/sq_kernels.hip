@@ -380,7 +380,8 @@ __device__ __forceinline__ uint64_t stream_tiles(const sqi::BatchDesc& d, uint32
     *bad += 1;
     return 0;
   }
-  return (len >> lg) + ((len & ((1ull << lg) - 1)) != 0);
+  const uint32_t lk = lg - (W == 8);  // tiles hold 2^lg * 4 bytes whatever the kind
+  return (len >> lk) + ((len & ((1ull << lk) - 1)) != 0);
 }
 
 // One workgroup: exclusive scan of per-stream tile counts into ts[0..m],
@@ -504,12 +505,13 @@ __device__ __forceinline__ TileDesc tile_desc(const sqi::BatchDesc& d, uint32_t 
                                               const uint32_t* map, uint64_t t) {
   TileDesc r;
   r.t = t;
-  const uint64_t T = 1ull << lg;
   const uint32_t s = map[t];
-  const uint64_t off = (t - ts[s]) << lg;
+  r.kind = d.kinds[s];
+  const uint32_t lk = lg - (r.kind == 2 || r.kind == 3);  // 2^lk outputs of the kind = 2^lg * 4 bytes
+  const uint64_t T = 1ull << lk;
+  const uint64_t off = (t - ts[s]) << lk;
   const uint64_t len = d.lens[s];
   r.cnt = len - off < T ? len - off : T;
-  r.kind = d.kinds[s];
   const bool split = r.kind > 3;  // two elements per counter; tiles hold an even count
   r.key = d.keys[s];
   r.ctr = d.ctr0s[s] + (split ? off >> 1 : off);
