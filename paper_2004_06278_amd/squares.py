@@ -173,6 +173,19 @@ def _ptr(t) -> int:
 _DTYPES = None
 
 
+def _out(out, nbytes: int, dtype):
+    """`out` if it is a contiguous CUDA tensor of at least nbytes bytes (the
+    library writes through a raw pointer and cannot check), else a new one."""
+    torch = _torch()
+    if out is None:
+        esize = torch.empty(0, dtype=dtype).element_size()
+        return torch.empty((nbytes + esize - 1) // esize, dtype=dtype, device="cuda")
+    have = out.numel() * out.element_size()
+    if have < nbytes:
+        raise ValueError(f"output tensor holds {have} bytes, the call writes {nbytes}")
+    return out
+
+
 def kind_dtype(kind: int):
     torch = _torch()
     return {U32: torch.uint32, F32: torch.float32, U64: torch.uint64, F64: torch.float64, U32X2: torch.uint32,
@@ -187,9 +200,7 @@ def cfg(block=1024, unroll=8, grid_per_cu=16, xcd_map=0, tile_log2=16) -> Launch
 def fill(kind: int, key: int, ctr0: int, n: int, out=None, stream=None, launch_cfg: LaunchCfg | None = None):
     """out[i] = kind's output at counter ctr0+i under key; returns `out` (a new
     CUDA tensor when not given)."""
-    torch = _torch()
-    if out is None:
-        out = torch.empty(n, dtype=kind_dtype(kind), device="cuda")
+    out = _out(out, n * KIND_BYTES.get(kind, 4), kind_dtype(kind) if kind in KIND_BYTES else _torch().uint8)
     key &= (1 << 64) - 1
     ctr0 &= (1 << 64) - 1
     if launch_cfg is None:
@@ -205,43 +216,37 @@ def fill_ptr(kind: int, key: int, ctr0: int, n: int, addr: int, stream=None) -> 
 
 
 def sq32_fill(key, ctr0, n, out=None, stream=None):
-    torch = _torch()
-    out = torch.empty(n, dtype=torch.uint32, device="cuda") if out is None else out
+    out = _out(out, 4 * n, _torch().uint32)
     check(lib().sq32_fill(key & (2**64 - 1), ctr0 & (2**64 - 1), n, _ptr(out), _stream(stream)))
     return out
 
 
 def sq64_fill(key, ctr0, n, out=None, stream=None):
-    torch = _torch()
-    out = torch.empty(n, dtype=torch.uint64, device="cuda") if out is None else out
+    out = _out(out, 8 * n, _torch().uint64)
     check(lib().sq64_fill(key & (2**64 - 1), ctr0 & (2**64 - 1), n, _ptr(out), _stream(stream)))
     return out
 
 
 def uniform_f32(key, ctr0, n, out=None, stream=None):
-    torch = _torch()
-    out = torch.empty(n, dtype=torch.float32, device="cuda") if out is None else out
+    out = _out(out, 4 * n, _torch().float32)
     check(lib().sq_uniform_f32(key & (2**64 - 1), ctr0 & (2**64 - 1), n, _ptr(out), _stream(stream)))
     return out
 
 
 def sq64x2_fill(key, ctr0, n, out=None, stream=None):
-    torch = _torch()
-    out = torch.empty(n, dtype=torch.uint32, device="cuda") if out is None else out
+    out = _out(out, 4 * n, _torch().uint32)
     check(lib().sq64x2_fill(key & (2**64 - 1), ctr0 & (2**64 - 1), n, _ptr(out), _stream(stream)))
     return out
 
 
 def uniform_f32x2(key, ctr0, n, out=None, stream=None):
-    torch = _torch()
-    out = torch.empty(n, dtype=torch.float32, device="cuda") if out is None else out
+    out = _out(out, 4 * n, _torch().float32)
     check(lib().sq_uniform_f32x2(key & (2**64 - 1), ctr0 & (2**64 - 1), n, _ptr(out), _stream(stream)))
     return out
 
 
 def uniform_f64(key, ctr0, n, out=None, stream=None):
-    torch = _torch()
-    out = torch.empty(n, dtype=torch.float64, device="cuda") if out is None else out
+    out = _out(out, 8 * n, _torch().float64)
     check(lib().sq_uniform_f64(key & (2**64 - 1), ctr0 & (2**64 - 1), n, _ptr(out), _stream(stream)))
     return out
 
@@ -272,9 +277,7 @@ def fill_strided(kind: int, key: int, ctr0: int, step: int, n: int, out=None, st
                  launch_cfg: LaunchCfg | None = None):
     """out[i] = kind's output at counter ctr0 + i*step (split kinds: word i%2 at
     ctr0 + (i//2)*step)."""
-    torch = _torch()
-    if out is None:
-        out = torch.empty(n, dtype=kind_dtype(kind), device="cuda")
+    out = _out(out, n * KIND_BYTES.get(kind, 4), kind_dtype(kind) if kind in KIND_BYTES else _torch().uint8)
     args = (kind, key & M64, ctr0 & M64, step & M64, n, _ptr(out))
     if launch_cfg is None:
         check(lib().sq_fill_strided(*args, _stream(stream)))
@@ -286,11 +289,11 @@ def fill_strided(kind: int, key: int, ctr0: int, step: int, n: int, out=None, st
 def fill_keys(kind: int, ctr: int, keys, out=None, stream=None, launch_cfg: LaunchCfg | None = None, m=None):
     """Key-counter mode: out[j] = kind's output at counter ctr under keys[j]
     (keys: a CUDA uint64/int64 tensor, or a device address with m given)."""
-    torch = _torch()
     if m is None:
         m = keys.numel()
-    if out is None:
-        out = torch.empty(m, dtype=kind_dtype(kind), device="cuda")
+    elif not isinstance(keys, int) and keys.numel() * keys.element_size() < 8 * m:
+        raise ValueError(f"keys tensor holds fewer than {m} keys")
+    out = _out(out, m * KIND_BYTES.get(kind, 4), kind_dtype(kind) if kind in KIND_BYTES else _torch().uint8)
     args = (kind, ctr & M64, _ptr(keys), m, _ptr(out))
     if launch_cfg is None:
         check(lib().sq_fill_keys(*args, _stream(stream)))
@@ -302,9 +305,7 @@ def fill_keys(kind: int, ctr: int, keys, out=None, stream=None, launch_cfg: Laun
 def make_keys(gen_key: int, ctr0: int, m: int, out=None, stream=None):
     """m distinct-digit keys generated on the device (key j from squares64 at
     counters ctr0 + 2j and ctr0 + 2j + 1 under gen_key)."""
-    torch = _torch()
-    if out is None:
-        out = torch.empty(m, dtype=torch.uint64, device="cuda")
+    out = _out(out, 8 * m, _torch().uint64)
     check(lib().sq_make_keys(gen_key & M64, ctr0 & M64, m, _ptr(out), _stream(stream)))
     return out
 
@@ -318,6 +319,7 @@ def reduce_workspace(n: int = 0):
 def reduce_async(kind: int, key: int, ctr0: int, n: int, result, ws, stream=None,
                  launch_cfg: LaunchCfg | None = None) -> None:
     """Launches the fused exact sum; `result` is a 32-byte CUDA tensor."""
+    _out(result, 32, _torch().uint8)
     args = (kind, key & (2**64 - 1), ctr0 & (2**64 - 1), n, _ptr(result), _ptr(ws), ws.numel() * ws.element_size())
     if launch_cfg is None:
         check(lib().sq_reduce(*args, _stream(stream)))
@@ -327,6 +329,7 @@ def reduce_async(kind: int, key: int, ctr0: int, n: int, result, ws, stream=None
 
 def reduce_strided_async(kind: int, key: int, ctr0: int, step: int, n: int, result, ws, stream=None,
                          launch_cfg: LaunchCfg | None = None) -> None:
+    _out(result, 32, _torch().uint8)
     args = (kind, key & M64, ctr0 & M64, step & M64, n, _ptr(result), _ptr(ws), ws.numel() * ws.element_size())
     if launch_cfg is None:
         check(lib().sq_reduce_strided(*args, _stream(stream)))
@@ -388,6 +391,7 @@ def batch_to_device(keys, ctr0s, lens, offs, kinds, out_bytes: int, out=None) ->
     kd = torch.from_numpy(np.ascontiguousarray(kinds, dtype=np.uint8)).cuda()
     if out is None:
         out = torch.zeros(max(out_bytes, 16), dtype=torch.uint8, device="cuda")
+    _out(out, out_bytes, torch.uint8)
     ws = torch.empty(int(lib().sq_batch_workspace_bytes(m, out_bytes)), dtype=torch.uint8, device="cuda")
     return DeviceBatch(u64(keys), u64(ctr0s), u64(lens), u64(offs), kd, m, out, out_bytes, ws)
 
@@ -405,6 +409,7 @@ def fill_streams(keys, ctr0s, lens, offs, kinds, out, out_bytes: int, stream=Non
     """One fill launch per stream from HOST descriptor arrays (numpy)."""
     import numpy as np
 
+    _out(out, out_bytes, _torch().uint8)
     arrs = [np.ascontiguousarray(a, dtype=np.uint64) for a in (keys, ctr0s, lens, offs)]
     kd = np.ascontiguousarray(kinds, dtype=np.uint8)
     m = kd.size

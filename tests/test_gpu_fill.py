@@ -89,6 +89,16 @@ def test_invalid_arguments(sq):
     sq.fill_ptr(0, 1, 0, 0, 0)  # n == 0: no launch, OK
     with pytest.raises(sq.SquaresError):
         sq.fill(0, 1, 0, 16, launch_cfg=sq.cfg(block=96))
+    # the binding refuses an output tensor too small for the call (the C ABI
+    # takes a raw pointer and cannot check)
+    with pytest.raises(ValueError):
+        sq.fill(0, 1, 0, 11, out=torch.empty(10, dtype=torch.uint32, device="cuda"))
+    with pytest.raises(ValueError):
+        sq.sq64_fill(1, 0, 6, out=torch.empty(5, dtype=torch.uint64, device="cuda"))
+    with pytest.raises(ValueError):
+        sq.fill_strided(2, 1, 0, 3, 6, out=torch.empty(40, dtype=torch.uint8, device="cuda"))
+    with pytest.raises(ValueError):
+        sq.make_keys(1, 0, 9, out=torch.empty(8, dtype=torch.uint64, device="cuda"))
 
 
 def test_argument_order_matches_paper_scalar(sq, oracle_mod):
