@@ -67,6 +67,33 @@ def test_fill_every_config(sq, oracle_mod, kind):
         assert got.tobytes() == ref.tobytes(), (c.as_dict(), first_diff(got, ref))
 
 
+@pytest.mark.parametrize("kind", KINDS)
+def test_fill_misaligned_every_order(sq, oracle_mod, kind):
+    """Start offsets that leave a head before the first aligned KiB, under each
+    chunk order and small and large workgroups: bytes equal the oracle's and
+    nothing outside the range is written."""
+    import torch
+
+    W, A = KIND_BYTES[kind], KIND_ALIGN[kind]
+    key, ctr0 = 0x2F8E5C1B7A3D9046, 2**64 - 40000
+    buf = torch.empty(100000 * 8 + 4096, dtype=torch.uint8, device="cuda")
+    cfgs = [sq.cfg(64, 4, 1, 2), sq.cfg(256, 1, 1, 2), sq.cfg(128, 8, 1, 2), sq.cfg(1024, 2, 1, 2),
+            sq.cfg(256, 4, 4, 0), sq.cfg(1024, 8, 2, 1)]
+    for n in (7, 1000, 70001):
+        ref = oracle_bytes(oracle_mod, kind, key, ctr0, n)
+        for off in (A, 1024 - A, 1024 + 3 * A):
+            for c in cfgs:
+                log(f"misaligned fill kind={kind} n={n} off={off} cfg={c.as_dict()}")
+                buf.fill_(0x3C)
+                sq.check(sq.lib().sq_fill_cfg(kind, key, ctr0, n, buf.data_ptr() + 64 + off, sq.ctypes.byref(c),
+                                              sq._stream()))
+                torch.cuda.synchronize()
+                host = to_host_bytes(buf)
+                got = host[64 + off: 64 + off + n * W]
+                assert got.tobytes() == ref.tobytes(), (c.as_dict(), first_diff(got, ref))
+                assert np.all(host[: 64 + off] == 0x3C) and np.all(host[64 + off + n * W:] == 0x3C)
+
+
 def test_invalid_arguments(sq):
     import torch
 
