@@ -54,7 +54,7 @@ KERNEL_SOURCES = ["paper_2004_06278_amd/csrc/sq_device.hpp", "paper_2004_06278_a
 # rocprofv3 kernel names (spaces and namespace removed) of the four step
 # operations: the unit-step instantiations of the fill and reduce templates
 KERNEL_NAMES = {"sq32_fill": r"k_fill<0,\d+,false>", "sq64_fill": r"k_fill<2,\d+,false>",
-                "fused_f32_sum": r"k_reduce<1,\d+,false>", "fused_f64_sum": r"k_reduce<3,\d+,false>"}
+                "fused_f32_sum": r"k_reduce(_queue)?<1,\d+,false>", "fused_f64_sum": r"k_reduce(_queue)?<3,\d+,false>"}
 
 
 def kernel_source_sha() -> str:
