@@ -3,9 +3,10 @@
 //  1. VALU issue rate per instruction class (lane-instructions per CU per
 //     clock at the nominal 2.4 GHz), from long loops of independent chains,
 //     with the shader clock read from clock64()/wall_clock64().
-//  2. HBM write ceiling: a store-only kernel (dwordx4 per lane, grid-stride
-//     over block*8-vector chunks, like the fill kernels without the
-//     generator) and hipMemsetD32 over 16 GiB.
+//  2. HBM write ceiling: store-only kernels (dwordx4 per lane) in the two
+//     launch shapes the fills use -- grid-stride over block*8-vector chunks,
+//     and one chunk of block*U vectors per workgroup -- and hipMemsetD32,
+//     each over 16 GiB.
 // Every kernel writes one value per thread into a buffer sized for the grid
 // (or stores inside [0, bytes)); nothing reads uninitialised memory.
 #include <hip/hip_runtime.h>
@@ -66,6 +67,19 @@ __global__ void k_store(u32x4* out, uint64_t nchunks, uint32_t v) {
       val.y += 1;
       p[u * B] = val;
     }
+  }
+}
+
+// One chunk of block*U vectors per workgroup (grid = chunks).
+template <int U>
+__global__ void k_store_chunk(u32x4* out, uint32_t v) {
+  const uint32_t B = blockDim.x;
+  u32x4 val = {v ^ threadIdx.x, v, v + 1, v + 2};
+  u32x4* p = out + (uint64_t)blockIdx.x * B * U + threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    val.y += 1;
+    p[(uint64_t)u * B] = val;
   }
 }
 
@@ -135,6 +149,15 @@ int main() {
       const float ms = best_ms([&] { k_store<<<grid, B>>>((u32x4*)o, nch, 7); }, 5);
       std::printf("| dwordx4 block %4d grid %5d | %7.3f | %7.1f |\n", B, grid, ms, bytes / (ms * 1e6));
     }
+  }
+  // one chunk per workgroup: 16 GiB / 16 B is a multiple of every B*U here,
+  // so the grid covers the buffer exactly
+  for (int B : {64, 256, 1024}) {
+    const uint64_t nvec = bytes / 16;
+    const float m1 = best_ms([&] { k_store_chunk<1><<<(uint32_t)(nvec / B), B>>>((u32x4*)o, 7); }, 5);
+    std::printf("| dwordx4 one chunk/workgroup, block %4d x 1 vector | %7.3f | %7.1f |\n", B, m1, bytes / (m1 * 1e6));
+    const float m4 = best_ms([&] { k_store_chunk<4><<<(uint32_t)(nvec / B / 4), B>>>((u32x4*)o, 7); }, 5);
+    std::printf("| dwordx4 one chunk/workgroup, block %4d x 4 vectors | %7.3f | %7.1f |\n", B, m4, bytes / (m4 * 1e6));
   }
   const float ms = best_ms([&] { CK(hipMemsetD32((hipDeviceptr_t)o, 5, bytes / 4)); }, 5);
   std::printf("| hipMemsetD32 | %7.3f | %7.1f |\n", ms, bytes / (ms * 1e6));
