@@ -193,10 +193,10 @@ def test_full_size_sampled(sq, oracle_mod, kind):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("kind", [0, 2])
+@pytest.mark.parametrize("kind", [0, 1, 2, 3])
 def test_full_size_complete(sq, oracle_mod, kind):
-    """Every one of the n = 2^32 squares32 (16 GiB) or squares64 (32 GiB)
-    outputs of the single-key workload, in the benchmark's launch
+    """Every one of the n = 2^32 outputs of the single-key workload (U32 and
+    F32: 16 GiB, U64 and F64: 32 GiB), in the benchmark's launch
     configuration, equals the oracle's: compared in chunks of 2^28 outputs,
     the oracle running on all host threads into a reused buffer."""
     import torch
@@ -207,17 +207,18 @@ def test_full_size_complete(sq, oracle_mod, kind):
     n, chunk = 1 << 32, 1 << 28
     log(f"full-size complete compare kind={kind} key={c.key:#x} ctr0={c.ctr0:#x} n={n}")
     out = sq.fill(kind, c.key, c.ctr0, n)
-    tdt = torch.int32 if kind == 0 else torch.int64
-    ndt = np.uint32 if kind == 0 else np.uint64
+    tdt = torch.int32 if KIND_BYTES[kind] == 4 else torch.int64
+    ndt = {0: np.uint32, 1: np.float32, 2: np.uint64, 3: np.float64}[kind]
     flat = out.view(tdt)
     host = torch.empty(chunk, dtype=tdt, pin_memory=True)
     ref = np.empty(chunk, dtype=ndt)
     for base in range(0, n, chunk):
         host.copy_(flat[base: base + chunk])
         oracle_mod.fill_into(kind, c.key, (c.ctr0 + base) % 2**64, ref, threads=HOST_THREADS)
-        got = host.numpy().view(ndt)
-        if not np.array_equal(got, ref):
-            bad = int(np.nonzero(got != ref)[0][0])
+        got = host.numpy()                      # compared as integers: bit equality, floats included
+        want = ref.view(got.dtype)
+        if not np.array_equal(got, want):
+            bad = int(np.nonzero(got != want)[0][0])
             pytest.fail(f"first mismatch at output {base + bad}")
     del out, flat
     torch.cuda.empty_cache()
