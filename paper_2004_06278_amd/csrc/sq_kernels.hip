@@ -395,9 +395,9 @@ __global__ __launch_bounds__(1024) void k_batch_scan(sqi::BatchDesc d, const uin
   __shared__ uint32_t errs;
   const uint32_t m = m_dev ? *m_dev : d.m;
   const uint32_t tid = threadIdx.x, B = blockDim.x;
-  const uint32_t per = (m + B - 1) / B;
-  const uint32_t b = tid * per < m ? tid * per : m;
-  const uint32_t e = b + per < m ? b + per : m;
+  const uint64_t per = ((uint64_t)m + B - 1) / B;  // 64-bit: no wrap for m near 2^32
+  const uint32_t b = (uint32_t)std::min<uint64_t>((uint64_t)tid * per, m);
+  const uint32_t e = (uint32_t)std::min<uint64_t>((uint64_t)b + per, m);
   if (tid == 0) errs = 0;
   __syncthreads();
   uint64_t local = 0;
