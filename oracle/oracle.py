@@ -75,6 +75,8 @@ def lib() -> ctypes.CDLL:
             L.oracle_fill_batch.restype = ctypes.c_int
             L.oracle_sum.argtypes = [ctypes.c_int, u64, u64, u64, vp]
             L.oracle_sum.restype = ctypes.c_int
+            L.oracle_trace_batch.argtypes = [vp, vp, u64, vp]
+            L.oracle_trace_batch.restype = None
             L.oracle_fill_strided.argtypes = [ctypes.c_int, u64, u64, u64, u64, vp]
             L.oracle_fill_strided.restype = ctypes.c_int
             L.oracle_fill_keys.argtypes = [ctypes.c_int, u64, vp, u64, vp]
@@ -152,6 +154,15 @@ def fill_into(kind: int, key: int, ctr0: int, out: np.ndarray, threads: int = 1)
         th.start()
     for th in ts:
         th.join()
+
+
+def trace_batch(ctrs, keys) -> np.ndarray:
+    """Per-round values (m x 5) of each (ctr, key) pair, as oracle_trace."""
+    ctrs = np.ascontiguousarray(ctrs, dtype=np.uint64)
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    out = np.empty((ctrs.size, 5), dtype=np.uint64)
+    lib().oracle_trace_batch(_ptr(ctrs), _ptr(keys), ctrs.size, _ptr(out))
+    return out
 
 
 def fill_strided(kind: int, key: int, ctr0: int, step: int, n: int) -> np.ndarray:

@@ -113,6 +113,12 @@ void oracle_trace(uint64_t ctr, uint64_t key, uint64_t trace[5])
     }
 }
 
+/* oracle_trace for m (ctr, key) pairs; trace row i is out[5i .. 5i+4]. */
+void oracle_trace_batch(const uint64_t *ctrs, const uint64_t *keys, uint64_t m, uint64_t *out)
+{
+    for (uint64_t i = 0; i < m; ++i) oracle_trace(ctrs[i], keys[i], out + 5 * i);
+}
+
 /* ------------------------------------------------------------------------
  * Uniform conversions.  Section 5 reports floating point outputs of 53-bit
  * precision but prints no formula.  The reading used here: the top 24 bits

@@ -178,6 +178,33 @@ def test_transcription_bigint_and_trace(oracle_mod):
         assert tr[3] ^ (tr[4] >> 32) == oracle_mod.squares64(c, k)
 
 
+def test_transcription_int128_every_round(oracle_mod, tmp_path):
+    """The oracle's per-round values against a second transcription with full
+    128-bit products and explicit truncation (tests/xcheck_int128.c, built
+    here with gcc), on 2^20 random pairs plus all pairs of edge words.  A
+    consistency check of the build, not counted as a pin."""
+    import ctypes
+    import os
+    import subprocess
+
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "xcheck_int128.c")
+    so = str(tmp_path / "libxcheck.so")
+    subprocess.run(["gcc", "-O2", "-shared", "-fPIC", "-o", so, src], check=True)
+    X = ctypes.CDLL(so)
+    vp = ctypes.c_void_p
+    X.xcheck_trace_batch.argtypes = [vp, vp, ctypes.c_uint64, vp]
+    g = np.random.Generator(np.random.PCG64(23))
+    ctrs = g.integers(0, 1 << 64, size=1 << 20, dtype=np.uint64, endpoint=False)
+    keys = g.integers(0, 1 << 64, size=1 << 20, dtype=np.uint64, endpoint=False)
+    edge = np.array(EDGE_WORDS, dtype=np.uint64)
+    ctrs = np.concatenate([ctrs, np.repeat(edge, edge.size)])
+    keys = np.concatenate([keys, np.tile(edge, edge.size)])
+    want = np.empty((ctrs.size, 5), dtype=np.uint64)
+    X.xcheck_trace_batch(ctrs.ctypes.data, keys.ctypes.data, ctrs.size, want.ctypes.data)
+    got = oracle_mod.trace_batch(ctrs, keys)
+    assert np.array_equal(got, want)
+
+
 # ---------------------------------------------------------------- bulk: counters
 def test_fill_is_counter_order(oracle_mod):
     o = oracle_mod
