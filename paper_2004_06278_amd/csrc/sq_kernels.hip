@@ -216,10 +216,12 @@ __device__ __forceinline__ void run_sum(uint64_t y, uint64_t cnt, uint64_t key, 
     // folded into the 128-bit total every 2^20 terms
     uint64_t i = 0;
     while (i < cnt) {
-      const uint64_t len = cnt - i < (1u << 20) ? cnt - i : (1u << 20);
+      // run lengths fit 32 bits: 32-bit loop control stays on the scalar
+      // unit when cnt is uniform
+      const uint32_t len = (uint32_t)(cnt - i < (1u << 20) ? cnt - i : (1u << 20));
       uint64_t s = 0;
       uint32_t carries = 0;
-      uint64_t j = 0;
+      uint32_t j = 0;
       for (; j + U <= len; j += U) {
         y = opaque(y);
 #pragma unroll
@@ -250,9 +252,9 @@ __device__ __forceinline__ void run_sum(uint64_t y, uint64_t cnt, uint64_t key, 
     constexpr uint64_t FLUSH = K == 3 ? 1024 : (K == 1 ? 256 : (1u << 20));
     uint64_t i = 0;
     while (i < cnt) {
-      const uint64_t len = cnt - i < FLUSH ? cnt - i : FLUSH;
+      const uint32_t len = (uint32_t)(cnt - i < FLUSH ? cnt - i : FLUSH);
       Part s = 0;
-      uint64_t j = 0;
+      uint32_t j = 0;
       for (; j + U <= len; j += U) {
         // opaque: otherwise loop-strength reduction rewrites every unrolled
         // y as base + (j+u)*key with its own induction variable, plus a
@@ -286,7 +288,12 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a) {
     cnt = a.n - begin < a.per ? a.n - begin : a.per;
   }
   uint64_t lo = 0, hi = 0;
-  run_sum<K, U, S>(a.y0 + t * a.ythread, cnt, a.key, a.dkey, lo, hi);
+  // A workgroup whose threads all have full runs passes the uniform count, so
+  // the loop control stays on the scalar unit.
+  if (((uint64_t)blockIdx.x + 1) * blockDim.x * a.per <= a.n)
+    run_sum<K, U, S>(a.y0 + t * a.ythread, a.per, a.key, a.dkey, lo, hi);
+  else
+    run_sum<K, U, S>(a.y0 + t * a.ythread, cnt, a.key, a.dkey, lo, hi);
   block_sum128(lo, hi);
   if (threadIdx.x == 0) {
     a.partials[2 * blockIdx.x] = lo;
@@ -312,8 +319,13 @@ __global__ __launch_bounds__(256) void k_reduce_queue(ReduceArgs a) {
     __syncthreads();  // every lane has read s_chunk before lane 0 overwrites it
     if (c >= a.nchunks) break;
     const uint64_t begin = c * chunk + (uint64_t)threadIdx.x * a.per;
-    const uint64_t cnt = begin < a.n ? (a.n - begin < a.per ? a.n - begin : a.per) : 0;
-    run_sum<K, U, S>(a.y0 + begin * a.dkey, cnt, a.key, a.dkey, lo, hi);
+    if ((c + 1) * chunk <= a.n) {
+      // whole chunk in range: the uniform count keeps the loop control scalar
+      run_sum<K, U, S>(a.y0 + begin * a.dkey, a.per, a.key, a.dkey, lo, hi);
+    } else {
+      const uint64_t cnt = begin < a.n ? (a.n - begin < a.per ? a.n - begin : a.per) : 0;
+      run_sum<K, U, S>(a.y0 + begin * a.dkey, cnt, a.key, a.dkey, lo, hi);
+    }
   }
   block_sum128(lo, hi);
   if (threadIdx.x == 0) {

@@ -70,7 +70,7 @@ sq_launch_cfg default_cfg(sq_op op, int kind, uint64_t n) {
     // resident grid taking chunks of 256 x 2^8 counters from the queue:
     // 4-6% faster than the static split on MI355X (no tail from the
     // slowest workgroups)
-    case SQ_OP_REDUCE: return sq_launch_cfg{256, 4, 8, 1, 8};
+    case SQ_OP_REDUCE: return sq_launch_cfg{256, 2, 8, 1, 8};
     // a persistent grid of two 256-lane workgroups per CU taking tiles of
     // 2^16 outputs from the queue: the fastest ragged-batch shape measured
     // on MI355X (dynamic balance with few descriptor loads per byte)
