@@ -41,6 +41,14 @@ __device__ __forceinline__ uint64_t opaque_uniform(uint64_t v) {
   return v;
 }
 
+// A value every lane of the wave holds (e.g. broadcast through LDS), moved
+// to scalar registers so the code that depends on it stays scalar.
+__device__ __forceinline__ uint64_t wave_uniform(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // The two instruction groups of a round, each pinned with a non-volatile
 // asm statement so that LLVM can schedule them but not rewrite them (with
 // plain C it duplicates the multiply-add, strength-reduces round 1's y*y + y

@@ -315,7 +315,7 @@ __global__ __launch_bounds__(256) void k_reduce_queue(ReduceArgs a) {
   while (true) {
     if (threadIdx.x == 0) s_chunk = atomicAdd(a.next, 1ull);
     __syncthreads();
-    const uint64_t c = s_chunk;
+    const uint64_t c = wave_uniform(s_chunk);  // same chunk for the whole workgroup
     __syncthreads();  // every lane has read s_chunk before lane 0 overwrites it
     if (c >= a.nchunks) break;
     const uint64_t begin = c * chunk + (uint64_t)threadIdx.x * a.per;
@@ -528,6 +528,13 @@ __device__ __forceinline__ TileDesc tile_desc(const sqi::BatchDesc& d, uint32_t 
   r.key = d.keys[s];
   r.ctr = d.ctr0s[s] + (split ? off >> 1 : off);
   r.p = d.out + d.offs[s] + off * ((r.kind == 2 || r.kind == 3) ? 8u : 4u);
+  // the same tile for every lane: keep its description in scalar registers
+  // so the tile's setup and loop control run on the scalar unit
+  r.key = wave_uniform(r.key);
+  r.ctr = wave_uniform(r.ctr);
+  r.cnt = wave_uniform(r.cnt);
+  r.p = (unsigned char*)wave_uniform((uint64_t)r.p);
+  r.kind = __builtin_amdgcn_readfirstlane(r.kind);
   return r;
 }
 
@@ -569,7 +576,7 @@ __global__ __launch_bounds__(1024) void k_batch_fill(sqi::BatchDesc d, uint32_t 
   while (true) {
     if (threadIdx.x == 0) s_tile = atomicAdd((unsigned long long*)&hdr->next_tile, 1ull);
     __syncthreads();
-    const uint64_t t = s_tile;
+    const uint64_t t = wave_uniform(s_tile);  // same tile for the whole workgroup
     __syncthreads();  // every lane has read s_tile before lane 0 overwrites it
     if (t >= total) break;
     batch_tile<U>(d, lg, ts, map, t);
