@@ -327,6 +327,11 @@ typedef struct {
     uint64_t chunk_cap;         /* outputs of one request per tick (>= 4096) */
     uint32_t n_streams;         /* concurrent ticks, 1..8 */
     uint32_t tile_log2;         /* tile of the tick kernel, 10..24 (0 = 14) */
+    uint64_t tick_bytes;        /* soft cap on one tick's output bytes (0 = none).  A tick
+                                   takes first the requests that finish within one chunk,
+                                   then the others round-robin from where the previous tick
+                                   stopped, until max_slots entries or this many bytes
+                                   (always at least one entry) */
 } sq_server_cfg;
 
 /* submit() flags */

@@ -134,6 +134,7 @@ struct sq_server {
   std::deque<uint64_t> queue;
   std::unordered_map<uint64_t, Req> reqs;
   std::vector<uint64_t> active;       // admitted, not complete, in admission order
+  size_t rr = 0;                      // round-robin start in `active` for ticks under a byte cap
   std::vector<uint32_t> free_slots;
   std::unordered_set<uint64_t> cancelled;
   Arena* arena = nullptr;
@@ -231,9 +232,9 @@ TickLane* sq_server::build_tick_locked() {
   TickHdr* th_ = (TickHdr*)L->host_buf;
   TickEntry* ent = (TickEntry*)(L->host_buf + sizeof(TickHdr));
   uint32_t m = 0;
-  for (uint64_t id : active) {
-    Req& r = reqs.at(id);
-    if (r.next >= r.n) continue;
+  uint64_t bytes = 0;
+  const uint64_t cap = cfg.tick_bytes ? cfg.tick_bytes : UINT64_MAX;
+  auto add = [&](Req& r) {
     const uint64_t cnt = std::min<uint64_t>(cfg.chunk_cap, r.n - r.next);
     ent[m].slot = r.slot;
     ent[m].pad = 0;
@@ -241,8 +242,24 @@ TickLane* sq_server::build_tick_locked() {
     ent[m].count = cnt;
     r.next += cnt;
     ++r.inflight;
-    L->reqs.push_back(id);
-    if (++m == cfg.max_slots) break;
+    L->reqs.push_back(r.id);
+    bytes += cnt * (uint64_t)kind_bytes(r.kind);
+    ++m;
+  };
+  // requests that finish within this chunk first (they leave the tick done),
+  // then the others from the round-robin position while under the byte cap
+  for (uint64_t id : active) {
+    if (m == cfg.max_slots) break;
+    Req& r = reqs.at(id);
+    if (r.next < r.n && r.n - r.next <= cfg.chunk_cap) add(r);
+  }
+  const size_t na = active.size();
+  for (size_t k = 0; k < na && m < cfg.max_slots && (bytes < cap || m == 0); ++k) {
+    const size_t i = (rr + k) % na;
+    Req& r = reqs.at(active[i]);
+    if (r.next >= r.n) continue;
+    add(r);
+    rr = i + 1;
   }
   if (m == 0) return nullptr;
   th_->entries = m;

@@ -48,7 +48,8 @@ class SumResult(ctypes.Structure):
 
 class ServerCfg(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_uint32),
-                ("chunk_cap", ctypes.c_uint64), ("n_streams", ctypes.c_uint32), ("tile_log2", ctypes.c_uint32)]
+                ("chunk_cap", ctypes.c_uint64), ("n_streams", ctypes.c_uint32), ("tile_log2", ctypes.c_uint32),
+                ("tick_bytes", ctypes.c_uint64)]
 
 
 class ServerStats(ctypes.Structure):
@@ -478,8 +479,8 @@ class Server:
     """Continuous-batching request loop (see sq_server_* in squares.h)."""
 
     def __init__(self, hbm_budget_bytes: int, max_slots: int = 4096, chunk_cap: int = 1 << 22, n_streams: int = 2,
-                 tile_log2: int = 0):
-        c = ServerCfg(hbm_budget_bytes, max_slots, chunk_cap, n_streams, tile_log2)
+                 tile_log2: int = 0, tick_bytes: int = 0):
+        c = ServerCfg(hbm_budget_bytes, max_slots, chunk_cap, n_streams, tile_log2, tick_bytes)
         h = ctypes.c_void_p()
         check(lib().sq_server_create(ctypes.byref(c), ctypes.byref(h)))
         self.h = h

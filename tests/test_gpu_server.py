@@ -32,11 +32,13 @@ def _mix(seed, r, max_log2):
     return [(int(tr.kinds[i]), int(tr.keys[i]), int(tr.ctr0s[i]), int(tr.sizes[i])) for i in range(r)]
 
 
-@pytest.mark.parametrize("n_streams,chunk_cap", [(1, 4096), (2, 1 << 14), (3, 1 << 20)])
-def test_server_alone_equals_mix_equals_oracle(sq, oracle_mod, n_streams, chunk_cap):
+@pytest.mark.parametrize("n_streams,chunk_cap,tick_bytes",
+                         [(1, 4096, 0), (2, 1 << 14, 0), (3, 1 << 20, 0), (2, 1 << 14, 100_000)])
+def test_server_alone_equals_mix_equals_oracle(sq, oracle_mod, n_streams, chunk_cap, tick_bytes):
     probe = (3, 0x6C8E9CF570932BD5, 2**64 - 70000, 150001)  # F64, wraps the counter, spans many ticks
-    log(f"server alone n_streams={n_streams} chunk_cap={chunk_cap}")
-    with sq.Server(64 << 20, max_slots=64, chunk_cap=chunk_cap, n_streams=n_streams) as srv:
+    log(f"server alone n_streams={n_streams} chunk_cap={chunk_cap} tick_bytes={tick_bytes}")
+    with sq.Server(64 << 20, max_slots=64, chunk_cap=chunk_cap, n_streams=n_streams,
+                   tick_bytes=tick_bytes) as srv:
         rid = srv.submit(*probe)
         srv.wait(rid)
         alone = to_host_bytes(srv.result_bytes(rid))
@@ -49,7 +51,8 @@ def test_server_alone_equals_mix_equals_oracle(sq, oracle_mod, n_streams, chunk_
     reqs += [(4 + (i % 2), 0x3F1E5D7C9B2A4068 + i, 2**64 - 1000 * i - 1, 1000 * i + 7) for i in range(1, 9)]
     reqs.insert(60, probe)
     log(f"server mix of {len(reqs)} requests")
-    with sq.Server(256 << 20, max_slots=48, chunk_cap=chunk_cap, n_streams=n_streams) as srv:
+    with sq.Server(256 << 20, max_slots=48, chunk_cap=chunk_cap, n_streams=n_streams,
+                   tick_bytes=tick_bytes) as srv:
         ids = [srv.submit(*q) for q in reqs]
         for rid in ids:
             srv.wait(rid)
