@@ -306,7 +306,10 @@ int sq_batch_plan_destroy(sq_batch_plan *plan);
 /* ------------------------------------------------------------------------
  * Serving: a continuous-batching request loop.  The generator is stateless
  * (Section 1, Section 6), so a request's whole state is (key, next counter,
- * outputs left); the server keeps it in a device slot table.
+ * outputs left).  The server keeps it on the host and hands each tick one
+ * self-contained descriptor per chunk (kind, key, first counter, count,
+ * output offset) in a pinned buffer, so concurrent ticks share no device
+ * state and never wait for each other.
  *  - submit() queues a request; a scheduler thread admits queued requests
  *    in arrival order while free slots and HBM budget allow (the request's
  *    output is carved from a device arena of hbm_budget_bytes owned by the
@@ -323,9 +326,14 @@ typedef struct sq_server sq_server;
 typedef struct {
     uint64_t hbm_budget_bytes;  /* output arena size (bytes); every admitted request's
                                    output lives here until released */
-    uint32_t max_slots;         /* admitted-but-unreleased requests, 1..65536 */
+    uint32_t max_slots;         /* requests admitted and not yet complete (also the most
+                                   chunks in one tick), 1..65536 */
     uint64_t chunk_cap;         /* outputs of one request per tick (>= 4096) */
-    uint32_t n_streams;         /* concurrent ticks, 1..8 */
+    uint32_t n_streams;         /* concurrent ticks (one HIP stream each), 1..8.  HIP binds
+                                   a stream to one of a few hardware queues (4 per process
+                                   by default) when it first runs work; in a process whose
+                                   other streams already hold queues, 2 lanes may share one
+                                   and serialize, so 4 is the robust choice */
     uint32_t tile_log2;         /* tile of the tick kernel, 10..24 (0 = 14) */
     uint64_t tick_bytes;        /* soft cap on one tick's output bytes (0 = none).  A tick
                                    takes first the requests that finish within one chunk,

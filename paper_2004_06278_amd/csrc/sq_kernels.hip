@@ -731,25 +731,22 @@ __global__ __launch_bounds__(256) void k_make_keys(uint64_t gen_key, uint64_t ct
 }
 
 // ============================================================== serving tick
-// Expands the tick's (slot, first, count) entries into batch descriptors
-// and advances each slot's device-side progress counter.
+// Copies the tick's chunk entries (read from the pinned host buffer) into
+// the batch descriptor arrays of the tick workspace.
 __global__ __launch_bounds__(256) void k_tick_expand(const sqi::TickHdr* th, const sqi::TickEntry* ent,
-                                                     sqi::SlotDev* slots, uint64_t* keys, uint64_t* ctr0s,
-                                                     uint64_t* lens, uint64_t* offs, uint8_t* kinds,
-                                                     uint32_t* m_out, uint32_t max_entries) {
+                                                     uint64_t* keys, uint64_t* ctr0s, uint64_t* lens,
+                                                     uint64_t* offs, uint8_t* kinds, uint32_t* m_out,
+                                                     uint32_t max_entries) {
   const uint32_t m = th->entries < max_entries ? th->entries : max_entries;
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) *m_out = m;
   if (i >= m) return;
   const sqi::TickEntry e = ent[i];
-  sqi::SlotDev& s = slots[e.slot];
-  const uint32_t W = (s.kind == 2 || s.kind == 3) ? 8u : 4u;
-  keys[i] = s.key;
-  ctr0s[i] = s.ctr0 + (s.kind > 3 ? e.first >> 1 : e.first);  // first is even for split kinds
+  keys[i] = e.key;
+  ctr0s[i] = e.ctr0;
   lens[i] = e.count;
-  offs[i] = s.out_off + e.first * W;
-  kinds[i] = (uint8_t)s.kind;
-  atomicAdd((unsigned long long*)&s.done, (unsigned long long)e.count);
+  offs[i] = e.out_off;
+  kinds[i] = (uint8_t)e.kind;
 }
 
 }  // namespace
@@ -941,7 +938,7 @@ size_t tick_ws_bytes(uint32_t max_entries, uint64_t arena_bytes) {
   return arrays + batch_ws_bytes(max_entries, arena_bytes);
 }
 
-hipError_t launch_tick(const void* tick_buf, SlotDev* slots, uint32_t max_entries, unsigned char* arena,
+hipError_t launch_tick(const void* tick_buf, uint32_t max_entries, unsigned char* arena,
                        uint64_t arena_bytes, void* tick_ws, const sq_launch_cfg& cfg, hipStream_t s) {
   unsigned char* w = (unsigned char*)tick_ws;
   uint64_t* keys = (uint64_t*)w;
@@ -954,8 +951,8 @@ hipError_t launch_tick(const void* tick_buf, SlotDev* slots, uint32_t max_entrie
   const TickHdr* th = (const TickHdr*)tick_buf;
   const TickEntry* ent = (const TickEntry*)((const unsigned char*)tick_buf + sizeof(TickHdr));
   const uint32_t blocks = (max_entries + 255) / 256;
-  hipLaunchKernelGGL(k_tick_expand, dim3(blocks), dim3(256), 0, s, th, ent, slots, keys, ctr0s, lens, offs, kinds,
-                     m_dev, max_entries);
+  hipLaunchKernelGGL(k_tick_expand, dim3(blocks), dim3(256), 0, s, th, ent, keys, ctr0s, lens, offs, kinds, m_dev,
+                     max_entries);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   BatchDesc d{keys, ctr0s, lens, offs, kinds, max_entries, arena, arena_bytes};

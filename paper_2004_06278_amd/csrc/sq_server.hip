@@ -1,9 +1,11 @@
 // Continuous-batching request server.
 //
 // The generators are stateless (a request is fully described by kind, key,
-// starting counter and length), so the whole state of an admitted request
-// is one 48-byte slot: key, ctr0, n, output offset, progress, kind.  Slots
-// live in a device table; admissions upload them on a control stream.
+// starting counter and length), so a chunk of a request is fully described
+// by (kind, key, counter of its first output, count, output offset).  The
+// host keeps each request's progress; a tick hands the device one such
+// self-contained entry per chunk, so ticks on different streams share no
+// device state and never wait for each other.
 //
 // A scheduler thread loops:
 //   1. retire ticks whose completion event has fired; a request completes
@@ -12,12 +14,11 @@
 //   2. admit queued requests in arrival order while a slot is free and the
 //      output arena (hbm_budget_bytes, owned by the server) has room;
 //   3. if a tick stream is idle and some admitted request has outputs left,
-//      build a tick: the next chunk (at most chunk_cap outputs) of every such
-//      request, written into that stream's pinned tick buffer, which the
+//      build a tick: the next chunk (at most chunk_cap outputs) of such
+//      requests, written into that stream's pinned tick buffer, which the
 //      tick's first kernel reads directly; then (with the lock released)
 //      replay the stream's captured graph (expand -> tile scan -> tile map ->
-//      persistent fill) after waiting for the control stream's latest slot
-//      upload.
+//      persistent fill).
 // Up to n_streams ticks are in flight at once, so requests admitted while
 // others run share the device with them.
 #include <hip/hip_runtime.h>
@@ -55,7 +56,6 @@ struct Req {
   uint32_t flags;
   St st = St::Queued;
   uint64_t off = 0, bytes = 0;  // arena range
-  uint32_t slot = 0;
   uint64_t next = 0;            // next output to schedule
   uint32_t inflight = 0;        // running ticks that hold a chunk of this request
   double t_submit = 0, t_done = 0;
@@ -123,10 +123,6 @@ struct sq_server {
   sq_launch_cfg lcfg{};
   int device = 0;
   unsigned char* arena_dev = nullptr;
-  SlotDev* slots_dev = nullptr;
-  SlotDev* slots_stage = nullptr;     // pinned, one record per slot
-  hipStream_t ctl = nullptr;
-  hipEvent_t ctl_ev = nullptr;
   std::vector<TickLane> lanes;
 
   std::mutex mu;
@@ -135,7 +131,6 @@ struct sq_server {
   std::unordered_map<uint64_t, Req> reqs;
   std::vector<uint64_t> active;       // admitted, not complete, in admission order
   size_t rr = 0;                      // round-robin start in `active` for ticks under a byte cap
-  std::vector<uint32_t> free_slots;
   std::unordered_set<uint64_t> cancelled;
   Arena* arena = nullptr;
   uint64_t next_id = 1;
@@ -149,7 +144,7 @@ struct sq_server {
 
   void loop();
   bool retire_locked();
-  bool admit_locked(std::vector<uint32_t>* new_slots);
+  bool admit_locked();
   TickLane* build_tick_locked();
   void finish_locked(Req& r);
 };
@@ -162,7 +157,6 @@ void sq_server::finish_locked(Req& r) {
   outputs += r.n;
   bytes_done += r.bytes;
   last_complete = r.t_done;
-  free_slots.push_back(r.slot);
   active.erase(std::find(active.begin(), active.end(), r.id));
   if (r.flags & SQ_SERVE_DISCARD) {
     arena->release(r.off, r.bytes);
@@ -192,28 +186,18 @@ bool sq_server::retire_locked() {
   return any;
 }
 
-// Admits queued requests (FIFO) while a slot and arena room exist.
-bool sq_server::admit_locked(std::vector<uint32_t>* new_slots) {
+// Admits queued requests (FIFO) while fewer than max_slots are active and
+// the arena has room.
+bool sq_server::admit_locked() {
   bool any = false;
-  while (!queue.empty() && !free_slots.empty()) {
+  while (!queue.empty() && active.size() < cfg.max_slots) {
     Req& r = reqs.at(queue.front());
     uint64_t off = 0;
     if (!arena->alloc(r.bytes, &off)) break;  // head of line waits for room
     queue.pop_front();
     r.off = off;
-    r.slot = free_slots.back();
-    free_slots.pop_back();
     r.st = St::Active;
     active.push_back(r.id);
-    SlotDev& sd = slots_stage[r.slot];
-    sd.key = r.key;
-    sd.ctr0 = r.ctr0;
-    sd.n = r.n;
-    sd.out_off = r.off;
-    sd.done = 0;
-    sd.kind = (uint32_t)r.kind;
-    sd.pad = 0;
-    new_slots->push_back(r.slot);
     ++admitted;
     any = true;
   }
@@ -236,14 +220,18 @@ TickLane* sq_server::build_tick_locked() {
   const uint64_t cap = cfg.tick_bytes ? cfg.tick_bytes : UINT64_MAX;
   auto add = [&](Req& r) {
     const uint64_t cnt = std::min<uint64_t>(cfg.chunk_cap, r.n - r.next);
-    ent[m].slot = r.slot;
-    ent[m].pad = 0;
-    ent[m].first = r.next;
+    const uint32_t W = (uint32_t)kind_bytes(r.kind);
+    ent[m].key = r.key;
+    // split kinds: chunks start at an even output, the low word of a pair
+    ent[m].ctr0 = r.ctr0 + (r.kind == SQ_U32X2 || r.kind == SQ_F32X2 ? r.next >> 1 : r.next);
     ent[m].count = cnt;
+    ent[m].out_off = r.off + r.next * W;
+    ent[m].kind = (uint32_t)r.kind;
+    ent[m].pad = 0;
     r.next += cnt;
     ++r.inflight;
     L->reqs.push_back(r.id);
-    bytes += cnt * (uint64_t)kind_bytes(r.kind);
+    bytes += cnt * W;
     ++m;
   };
   // requests that finish within this chunk first (they leave the tick done),
@@ -269,12 +257,11 @@ TickLane* sq_server::build_tick_locked() {
 }
 
 // The scheduler.  Lane state (busy, finished, event status) belongs to this
-// thread; request, queue, slot and arena state is shared and changed only
-// under `mu`.  HIP calls (event queries, slot uploads, graph launches) run
+// thread; request, queue and arena state is shared and changed only
+// under `mu`.  HIP calls (event queries, graph launches) run
 // with the lock released, so submit()/poll() never wait behind them.
 void sq_server::loop() {
   (void)hipSetDevice(device);
-  std::vector<uint32_t> new_slots;
   std::vector<TickLane*> to_launch;
   for (;;) {
     for (auto& L : lanes) {
@@ -285,26 +272,20 @@ void sq_server::loop() {
       L.finished = true;
     }
     bool progress = false, inflight = false, exit_now = false;
-    new_slots.clear();
     to_launch.clear();
     {
       std::unique_lock<std::mutex> lk(mu);
       progress |= retire_locked();
-      progress |= admit_locked(&new_slots);
+      progress |= admit_locked();
       while (TickLane* L = build_tick_locked()) to_launch.push_back(L);
       inflight = std::any_of(lanes.begin(), lanes.end(), [](const TickLane& l) { return l.busy; });
       if (stop && !inflight && active.empty() && queue.empty()) exit_now = true;
-      else if (!inflight && !progress && new_slots.empty()) cv_work.wait_for(lk, std::chrono::milliseconds(20));
+      else if (!inflight && !progress) cv_work.wait_for(lk, std::chrono::milliseconds(20));
     }
     if (exit_now) break;
     hipError_t e = hipSuccess;
-    for (uint32_t slot : new_slots)
-      if (e == hipSuccess)
-        e = hipMemcpyAsync(slots_dev + slot, slots_stage + slot, sizeof(SlotDev), hipMemcpyHostToDevice, ctl);
-    if (!new_slots.empty() && e == hipSuccess) e = hipEventRecord(ctl_ev, ctl);
     std::atomic_thread_fence(std::memory_order_seq_cst);  // tick entries visible before the launch doorbell
     for (TickLane* L : to_launch) {
-      if (e == hipSuccess) e = hipStreamWaitEvent(L->stream, ctl_ev, 0);
       if (e == hipSuccess) e = hipGraphLaunch(L->exec, L->stream);
       if (e == hipSuccess) e = hipEventRecord(L->done, L->stream);
       if (e != hipSuccess) {  // the lane never runs: retire it at once with the error
@@ -329,10 +310,6 @@ static void server_free(sq_server* s) {
     if (L.host_buf) (void)hipHostFree(L.host_buf);
     if (L.ws) (void)hipFree(L.ws);
   }
-  if (s->ctl_ev) (void)hipEventDestroy(s->ctl_ev);
-  if (s->ctl) (void)hipStreamDestroy(s->ctl);
-  if (s->slots_stage) (void)hipHostFree(s->slots_stage);
-  if (s->slots_dev) (void)hipFree(s->slots_dev);
   if (s->arena_dev) (void)hipFree(s->arena_dev);
   delete s->arena;
   delete s;
@@ -359,11 +336,6 @@ int sq_server_create(const sq_server_cfg* cfg, sq_server** out) {
   if (cfg->tile_log2) s->lcfg.tile_log2 = cfg->tile_log2;
   s->arena = new Arena(cfg->hbm_budget_bytes);
   hipError_t e = hipMalloc((void**)&s->arena_dev, cfg->hbm_budget_bytes);
-  if (e == hipSuccess) e = hipMalloc((void**)&s->slots_dev, sizeof(SlotDev) * cfg->max_slots);
-  if (e == hipSuccess) e = hipHostMalloc((void**)&s->slots_stage, sizeof(SlotDev) * cfg->max_slots, hipHostMallocDefault);
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->ctl, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ctl_ev, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventRecord(s->ctl_ev, s->ctl);
   s->lanes.resize(cfg->n_streams);
   const size_t tbuf = sizeof(TickHdr) + sizeof(TickEntry) * (size_t)cfg->max_slots;
   for (auto& L : s->lanes) {
@@ -377,8 +349,8 @@ int sq_server_create(const sq_server_cfg* cfg, sq_server** out) {
     // capture expand -> scan -> fill once over this lane's fixed buffers
     e = hipStreamBeginCapture(L.stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-      hipError_t le = launch_tick(L.host_buf, s->slots_dev, cfg->max_slots, s->arena_dev, cfg->hbm_budget_bytes,
-                                  L.ws, s->lcfg, L.stream);
+      hipError_t le = launch_tick(L.host_buf, cfg->max_slots, s->arena_dev, cfg->hbm_budget_bytes, L.ws, s->lcfg,
+                                  L.stream);
       hipError_t ee = hipStreamEndCapture(L.stream, &L.graph);
       e = le != hipSuccess ? le : ee;
     }
@@ -389,7 +361,6 @@ int sq_server_create(const sq_server_cfg* cfg, sq_server** out) {
     server_free(s);
     return r;
   }
-  for (uint32_t i = 0; i < cfg->max_slots; ++i) s->free_slots.push_back(cfg->max_slots - 1 - i);
   s->th = std::thread([s] { s->loop(); });
   *out = s;
   return SQ_OK;

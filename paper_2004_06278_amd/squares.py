@@ -478,7 +478,7 @@ def autotune(op_mask: int = 7, max_bytes: int = 8 << 30, save_path: str | None =
 class Server:
     """Continuous-batching request loop (see sq_server_* in squares.h)."""
 
-    def __init__(self, hbm_budget_bytes: int, max_slots: int = 4096, chunk_cap: int = 1 << 22, n_streams: int = 2,
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 4096, chunk_cap: int = 1 << 22, n_streams: int = 4,
                  tile_log2: int = 0, tick_bytes: int = 0):
         c = ServerCfg(hbm_budget_bytes, max_slots, chunk_cap, n_streams, tile_log2, tick_bytes)
         h = ctypes.c_void_p()
