@@ -513,7 +513,13 @@ int sq_server_destroy(sq_server* s) {
   }
   s->th.join();
   std::string fatal = s->fatal;
-  hipError_t e = hipDeviceSynchronize();
+  // the scheduler exits only with no tick in flight; synchronizing the lane
+  // streams (not the device) leaves the caller's other work alone
+  hipError_t e = hipSuccess;
+  for (auto& L : s->lanes) {
+    const hipError_t le = hipStreamSynchronize(L.stream);
+    if (e == hipSuccess) e = le;
+  }
   server_free(s);
   if (!fatal.empty()) return fail(SQ_EHIP, "server failed: " + fatal);
   if (e != hipSuccess) return fail_hip(e, "server drain");
