@@ -60,13 +60,14 @@ bool cfg_valid(sq_op op, const sq_launch_cfg& c) {
 sq_launch_cfg default_cfg(sq_op op, int kind, uint64_t n) {
   (void)n;
   switch (op) {
-    // One 4 KiB chunk per workgroup (grid = chunks): the fastest fill shapes
-    // measured on MI355X.  Small one-shot chunks keep the write front narrow
-    // and let retiring workgroups be replaced anywhere.  squares32 kinds do
-    // more VALU work per byte and do best with one wave per workgroup and 4
-    // vectors per lane; squares64 kinds with 256 lanes and one vector each.
+    // One 4 KiB chunk per workgroup (grid = chunks), 256 lanes with one
+    // 16-byte vector each: the fastest fill shape measured on MI355X both
+    // back to back and right after a compute-bound kernel.  Small one-shot
+    // chunks keep the write front narrow and let retiring workgroups be
+    // replaced anywhere.
     case SQ_OP_FILL:
-      return (kind == SQ_U32 || kind == SQ_F32) ? sq_launch_cfg{64, 4, 1, 2, 16} : sq_launch_cfg{256, 1, 1, 2, 16};
+      (void)kind;
+      return sq_launch_cfg{256, 1, 1, 2, 16};
     // resident grid taking chunks of 256 x 2^8 counters from the queue:
     // 4-6% faster than the static split on MI355X (no tail from the
     // slowest workgroups)
@@ -133,12 +134,14 @@ __global__ void k_count_diff(const uint32_t* a, const uint32_t* b, uint64_t word
 struct Scratch {
   void* a = nullptr;
   void* b = nullptr;
+  void* ctx = nullptr;                // result and workspace of the context kernel
   unsigned long long* bad = nullptr;
   hipStream_t s = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   ~Scratch() {
     if (a) (void)hipFree(a);
     if (b) (void)hipFree(b);
+    if (ctx) (void)hipFree(ctx);
     if (bad) (void)hipFree(bad);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
@@ -185,6 +188,47 @@ static hipError_t time_pair(Scratch& S, FA inc, FB cand, int reps, float* ms_inc
   std::sort(b.begin(), b.end());
   *ms_inc = a[a.size() / 2];
   *ms_cand = b[b.size() / 2];
+  return hipSuccess;
+}
+
+// The same with a context: each timed launch follows an untimed run of
+// `ctx` and is then repeated back to back, and each side scores the sum of
+// its two medians.  The shader clock a launch meets depends on what ran
+// before it (a compute-bound kernel leaves it high, a run of memory-bound
+// launches lower), and on MI355X the best fill shape differs between the
+// two: squares32 with 64 lanes x 4 vectors takes 2.62 ms back to back but
+// 2.86 ms after a fused sum, 256 lanes x 1 vector 2.74 ms and 2.50 ms.
+template <typename FA, typename FB, typename FC>
+static hipError_t time_pair_ctx(Scratch& S, FA inc, FB cand, FC ctx, int reps, float* score_inc,
+                                float* score_cand) {
+  hipError_t e = inc();
+  if (e == hipSuccess) e = cand();
+  if (e != hipSuccess) return e;
+  std::vector<float> t[2][2];  // [side][after ctx, back to back]
+  for (int r = 0; r < reps; ++r) {
+    for (int which = 0; which < 2; ++which) {
+      if ((e = ctx()) != hipSuccess) return e;
+      for (int k = 0; k < 2; ++k) {
+        if ((e = hipEventRecord(S.e0, S.s)) != hipSuccess) return e;
+        if ((e = which == 0 ? inc() : cand()) != hipSuccess) return e;
+        if ((e = hipEventRecord(S.e1, S.s)) != hipSuccess) return e;
+        if ((e = hipEventSynchronize(S.e1)) != hipSuccess) return e;
+        float ms = 0;
+        if ((e = hipEventElapsedTime(&ms, S.e0, S.e1)) != hipSuccess) return e;
+        t[which][k].push_back(ms);
+      }
+    }
+  }
+  float score[2];
+  for (int w = 0; w < 2; ++w) {
+    score[w] = 0;
+    for (int k = 0; k < 2; ++k) {
+      std::sort(t[w][k].begin(), t[w][k].end());
+      score[w] += t[w][k][t[w][k].size() / 2];
+    }
+  }
+  *score_inc = score[0];
+  *score_cand = score[1];
   return hipSuccess;
 }
 
@@ -278,6 +322,7 @@ int sq_autotune(uint32_t op_mask, uint64_t max_bytes, const char* save_path) {
   hipError_t e = hipMalloc(&S.a, half);
   if (e == hipSuccess) e = hipMalloc(&S.b, half);
   if (e == hipSuccess) e = hipMalloc((void**)&S.bad, 64);
+  if (e == hipSuccess) e = hipMalloc(&S.ctx, 4096 + sq_reduce_workspace_bytes(0));
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&S.s, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreate(&S.e0);
   if (e == hipSuccess) e = hipEventCreate(&S.e1);
@@ -285,6 +330,13 @@ int sq_autotune(uint32_t op_mask, uint64_t max_bytes, const char* save_path) {
   const uint64_t key = 0x9B2F6E1D4C8A0357ull, ctr0 = 0xFFFFFFFFFFFF0000ull;  // crosses 2^64 on purpose
 
   if (op_mask & (1u << SQ_OP_FILL)) {
+    // context of every timed fill: a compute-bound fused F64 sum over 2^31
+    // counters (about 1 ms), as when generation alternates with compute
+    const sq_launch_cfg ctx_cfg = default_cfg(SQ_OP_REDUCE, SQ_F64, 1ull << 31);
+    auto ctx = [&] {
+      return launch_reduce(SQ_F64, key, ctr0, 1ull << 31, (sq_sum_result*)S.ctx, (unsigned char*)S.ctx + 4096,
+                           ctx_cfg, S.s);
+    };
     for (int kind = 0; kind < kKinds; ++kind) {
       const uint64_t W = kind_bytes(kind);
       for (int b = 0; b < kBuckets; ++b) {
@@ -294,8 +346,9 @@ int sq_autotune(uint32_t op_mask, uint64_t max_bytes, const char* save_path) {
         if ((e = launch_fill(kind, key, ctr0, n, (unsigned char*)S.b, ref, S.s)) != hipSuccess) break;
         std::swap(S.a, S.b);  // reference now in a
         // The default is the first incumbent.  Each candidate is timed in
-        // alternation with the incumbent and replaces it when its median is
-        // 2% lower (below timing noise) and its bytes equal the reference's.
+        // alternation with the incumbent (after the context kernel and back
+        // to back) and replaces it when its score is 2% lower (below timing
+        // noise) and its bytes equal the reference's.
         sq_launch_cfg best_c = ref;
         // candidates: one chunk per workgroup for every block and unroll,
         // and the grid-stride orders for the larger shapes
@@ -309,9 +362,9 @@ int sq_autotune(uint32_t op_mask, uint64_t max_bytes, const char* save_path) {
         for (const sq_launch_cfg& c : cands) {
           float ms_inc = 0, ms = 0;
           const sq_launch_cfg inc = best_c;
-          e = time_pair(
+          e = time_pair_ctx(
               S, [&] { return launch_fill(kind, key, ctr0, n, (unsigned char*)S.b, inc, S.s); },
-              [&] { return launch_fill(kind, key, ctr0, n, (unsigned char*)S.b, c, S.s); }, 5, &ms_inc, &ms);
+              [&] { return launch_fill(kind, key, ctr0, n, (unsigned char*)S.b, c, S.s); }, ctx, 5, &ms_inc, &ms);
           if (e != hipSuccess) break;
           bool same = false;
           if ((e = same_bytes(S, n * W, &same)) != hipSuccess) break;
