@@ -306,10 +306,13 @@ int sq_batch_plan_destroy(sq_batch_plan *plan);
 /* ------------------------------------------------------------------------
  * Serving: a continuous-batching request loop.  The generator is stateless
  * (Section 1, Section 6), so a request's whole state is (key, next counter,
- * outputs left).  The server keeps it on the host and hands each tick one
- * self-contained descriptor per chunk (kind, key, first counter, count,
- * output offset) in a pinned buffer, so concurrent ticks share no device
- * state and never wait for each other.
+ * outputs left).  Each admitted request's key and counter base (with its
+ * kind and output offset) live in a device slot; a tick names each chunk
+ * as (slot, first output, count) in a pinned buffer that the tick's first
+ * kernel reads, and the kernel derives the chunk's counters from the slot.
+ * A request's entries carry its description until one of its ticks has
+ * completed, and the tick writes it into the slot, so there are no copies
+ * on a control stream and concurrent ticks never wait for each other.
  *  - submit() queues a request; a scheduler thread admits queued requests
  *    in arrival order while free slots and HBM budget allow (the request's
  *    output is carved from a device arena of hbm_budget_bytes owned by the

@@ -103,27 +103,10 @@ static_assert(sizeof(BatchHdr) == 64, "header is 64 bytes");
 uint64_t batch_max_tiles(uint32_t m, uint64_t out_bytes);
 size_t batch_ws_bytes(uint32_t m, uint64_t out_bytes);
 hipError_t launch_batch(const BatchDesc& d, void* ws, const sq_launch_cfg& cfg, hipStream_t s);
+// The batch kernels with the stream count read on the device from m_dev
+// (nullptr: d.m), as a serving tick needs.
+hipError_t launch_batch_body(const BatchDesc& d, const uint32_t* m_dev, void* ws, const sq_launch_cfg& cfg,
+                             hipStream_t s);
 
-// Serving tick: one self-contained entry per chunk (one chunk of one request).
-struct TickEntry {
-  uint64_t key;
-  uint64_t ctr0;       // counter of the chunk's first output (split kinds: of its first word pair)
-  uint64_t count;      // outputs in this chunk
-  uint64_t out_off;    // byte offset of the chunk's first output in the arena
-  uint32_t kind;
-  uint32_t pad;
-};
-static_assert(sizeof(TickEntry) == 40, "tick entry is 40 bytes");
-struct TickHdr {
-  uint32_t entries;    // number of TickEntry that follow
-  uint32_t pad;
-  uint64_t pad2[7];
-};
-static_assert(sizeof(TickHdr) == 64, "tick header is 64 bytes");
-// tick buffer = TickHdr + max_entries TickEntry (device); tick ws holds the
-// expanded batch descriptors and tile scan for up to max_entries streams.
-size_t tick_ws_bytes(uint32_t max_entries, uint64_t arena_bytes);
-hipError_t launch_tick(const void* tick_buf, uint32_t max_entries, unsigned char* arena,
-                       uint64_t arena_bytes, void* tick_ws, const sq_launch_cfg& cfg, hipStream_t s);
 
 }  // namespace sqi

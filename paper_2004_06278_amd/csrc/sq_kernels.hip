@@ -1,7 +1,6 @@
 // gfx950 kernels of the Squares RNG: bulk fill (unit and other counter
 // increments), fused exact reduce, ragged batch (tile scan, tile map and a
-// tile-queue fill), key-counter mode, key generation and the serving tick
-// expansion.
+// tile-queue fill), key-counter mode and key generation.
 //
 // Every kernel is plain VALU integer code (no MFMA: nothing is a
 // contraction).  Fills are bound by HBM write bandwidth: each lane produces
@@ -730,25 +729,6 @@ __global__ __launch_bounds__(256) void k_make_keys(uint64_t gen_key, uint64_t ct
   }
 }
 
-// ============================================================== serving tick
-// Copies the tick's chunk entries (read from the pinned host buffer) into
-// the batch descriptor arrays of the tick workspace.
-__global__ __launch_bounds__(256) void k_tick_expand(const sqi::TickHdr* th, const sqi::TickEntry* ent,
-                                                     uint64_t* keys, uint64_t* ctr0s, uint64_t* lens,
-                                                     uint64_t* offs, uint8_t* kinds, uint32_t* m_out,
-                                                     uint32_t max_entries) {
-  const uint32_t m = th->entries < max_entries ? th->entries : max_entries;
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) *m_out = m;
-  if (i >= m) return;
-  const sqi::TickEntry e = ent[i];
-  keys[i] = e.key;
-  ctr0s[i] = e.ctr0;
-  lens[i] = e.count;
-  offs[i] = e.out_off;
-  kinds[i] = (uint8_t)e.kind;
-}
-
 }  // namespace
 
 // ============================================================== launchers
@@ -899,8 +879,8 @@ size_t batch_ws_bytes(uint32_t m, uint64_t out_bytes) {
   return (b + 255) & ~(size_t)255;
 }
 
-static hipError_t launch_batch_body(const BatchDesc& d, const uint32_t* m_dev, void* ws, const sq_launch_cfg& cfg,
-                                    hipStream_t s) {
+hipError_t launch_batch_body(const BatchDesc& d, const uint32_t* m_dev, void* ws, const sq_launch_cfg& cfg,
+                             hipStream_t s) {
   BatchHdr* hdr = (BatchHdr*)ws;
   uint64_t* ts = (uint64_t*)((unsigned char*)ws + sizeof(BatchHdr));
   uint32_t* map = (uint32_t*)(ts + (size_t)d.m + 1);
@@ -929,34 +909,6 @@ static hipError_t launch_batch_body(const BatchDesc& d, const uint32_t* m_dev, v
 
 hipError_t launch_batch(const BatchDesc& d, void* ws, const sq_launch_cfg& cfg, hipStream_t s) {
   return launch_batch_body(d, nullptr, ws, cfg, s);
-}
-
-// tick ws layout: keys, ctr0s, lens, offs (u64 x max each), kinds (u8 x max,
-// padded), m (u32, padded to 256), then the batch workspace over the arena.
-size_t tick_ws_bytes(uint32_t max_entries, uint64_t arena_bytes) {
-  const size_t arrays = 32ull * max_entries + (((size_t)max_entries + 255) & ~(size_t)255) + 256;
-  return arrays + batch_ws_bytes(max_entries, arena_bytes);
-}
-
-hipError_t launch_tick(const void* tick_buf, uint32_t max_entries, unsigned char* arena,
-                       uint64_t arena_bytes, void* tick_ws, const sq_launch_cfg& cfg, hipStream_t s) {
-  unsigned char* w = (unsigned char*)tick_ws;
-  uint64_t* keys = (uint64_t*)w;
-  uint64_t* ctr0s = keys + max_entries;
-  uint64_t* lens = ctr0s + max_entries;
-  uint64_t* offs = lens + max_entries;
-  uint8_t* kinds = (uint8_t*)(offs + max_entries);
-  uint32_t* m_dev = (uint32_t*)(kinds + (((size_t)max_entries + 255) & ~(size_t)255));
-  void* bws = (unsigned char*)m_dev + 256;
-  const TickHdr* th = (const TickHdr*)tick_buf;
-  const TickEntry* ent = (const TickEntry*)((const unsigned char*)tick_buf + sizeof(TickHdr));
-  const uint32_t blocks = (max_entries + 255) / 256;
-  hipLaunchKernelGGL(k_tick_expand, dim3(blocks), dim3(256), 0, s, th, ent, keys, ctr0s, lens, offs, kinds, m_dev,
-                     max_entries);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  BatchDesc d{keys, ctr0s, lens, offs, kinds, max_entries, arena, arena_bytes};
-  return launch_batch_body(d, m_dev, bws, cfg, s);
 }
 
 }  // namespace sqi

@@ -1,11 +1,15 @@
 // Continuous-batching request server.
 //
 // The generators are stateless (a request is fully described by kind, key,
-// starting counter and length), so a chunk of a request is fully described
-// by (kind, key, counter of its first output, count, output offset).  The
-// host keeps each request's progress; a tick hands the device one such
-// self-contained entry per chunk, so ticks on different streams share no
-// device state and never wait for each other.
+// starting counter and length), so an admitted request's key and counter
+// state is one 32-byte device slot: key, first counter, output offset, kind.
+// A tick names each chunk as (slot, first output, count) and its first
+// kernel derives the chunk's counter and output address from the slot.  The
+// slot is written by the request's own ticks: until a tick holding the
+// request has completed, its entries carry the whole description, which the
+// tick stores in the slot (identical values from any lane), so there are no
+// copies on a control stream and ticks on different lanes never wait for
+// each other; chunks of one request may run on several lanes at once.
 //
 // A scheduler thread loops:
 //   1. retire ticks whose completion event has fired; a request completes
@@ -56,6 +60,8 @@ struct Req {
   uint32_t flags;
   St st = St::Queued;
   uint64_t off = 0, bytes = 0;  // arena range
+  uint32_t slot = 0;            // device slot holding the key and counter state
+  bool slot_ready = false;      // a tick holding this request has completed (the slot is written)
   uint64_t next = 0;            // next output to schedule
   uint32_t inflight = 0;        // running ticks that hold a chunk of this request
   double t_submit = 0, t_done = 0;
@@ -103,6 +109,99 @@ class Arena {
   uint64_t used_ = 0;
 };
 
+// ---------------------------------------------------------------- slots and ticks
+// An admitted request's key and counter base live in a device slot for the
+// request's lifetime; each tick names a chunk as (slot, first,
+// count).  Until a tick holding the request has completed, its entries also
+// carry the whole description (init = 1), which the tick writes into the
+// slot (every such write stores the same values).
+struct SlotDev {
+  uint64_t key;
+  uint64_t ctr0;       // counter of the request's first output
+  uint64_t out_off;    // arena byte offset of the request's output
+  uint32_t kind;
+  uint32_t pad;
+};
+static_assert(sizeof(SlotDev) == 32, "slot is 32 bytes");
+struct TickEntry {
+  uint32_t slot;
+  uint32_t init;
+  uint64_t first;      // first output of the chunk within the request (even for split kinds)
+  uint64_t count;      // outputs in this chunk
+  uint64_t key;        // init only
+  uint64_t ctr0;       // init only
+  uint64_t out_off;    // init only
+  uint32_t kind;       // init only
+  uint32_t pad;
+};
+static_assert(sizeof(TickEntry) == 56, "tick entry is 56 bytes");
+struct TickHdr {
+  uint32_t entries;    // number of TickEntry that follow
+  uint32_t pad;
+  uint64_t pad2[7];
+};
+static_assert(sizeof(TickHdr) == 64, "tick header is 64 bytes");
+
+// ---------------------------------------------------------------- tick expansion
+// Turns the tick's chunk entries into batch descriptors: a chunk's key,
+// first counter and output offset come from its request's device slot
+// (written first from the entry while the entry carries the description).
+__global__ __launch_bounds__(256) void k_tick_expand(const TickHdr* th, const TickEntry* ent,
+                                                     SlotDev* slots, uint64_t* keys, uint64_t* ctr0s,
+                                                     uint64_t* lens, uint64_t* offs, uint8_t* kinds,
+                                                     uint32_t* m_out, uint32_t max_entries) {
+  const uint32_t m = th->entries < max_entries ? th->entries : max_entries;
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *m_out = m;
+  if (i >= m) return;
+  const TickEntry e = ent[i];
+  SlotDev s;
+  if (e.init) {
+    s.key = e.key;
+    s.ctr0 = e.ctr0;
+    s.out_off = e.out_off;
+    s.kind = e.kind;
+    s.pad = 0;
+    slots[e.slot] = s;
+  } else {
+    s = slots[e.slot];
+  }
+  const uint32_t W = (s.kind == 2 || s.kind == 3) ? 8u : 4u;
+  keys[i] = s.key;
+  ctr0s[i] = s.ctr0 + (s.kind > 3 ? e.first >> 1 : e.first);  // split kinds: two outputs per counter
+  lens[i] = e.count;
+  offs[i] = s.out_off + e.first * W;
+  kinds[i] = (uint8_t)s.kind;
+}
+
+// tick ws layout: keys, ctr0s, lens, offs (u64 x max each), kinds (u8 x max,
+// padded), m (u32, padded to 256), then the batch workspace over the arena.
+size_t tick_ws_bytes(uint32_t max_entries, uint64_t arena_bytes) {
+  const size_t arrays = 32ull * max_entries + (((size_t)max_entries + 255) & ~(size_t)255) + 256;
+  return arrays + batch_ws_bytes(max_entries, arena_bytes);
+}
+
+hipError_t launch_tick(const void* tick_buf, SlotDev* slots, uint32_t max_entries, unsigned char* arena,
+                       uint64_t arena_bytes, void* tick_ws, const sq_launch_cfg& cfg, hipStream_t s) {
+  unsigned char* w = (unsigned char*)tick_ws;
+  uint64_t* keys = (uint64_t*)w;
+  uint64_t* ctr0s = keys + max_entries;
+  uint64_t* lens = ctr0s + max_entries;
+  uint64_t* offs = lens + max_entries;
+  uint8_t* kinds = (uint8_t*)(offs + max_entries);
+  uint32_t* m_dev = (uint32_t*)(kinds + (((size_t)max_entries + 255) & ~(size_t)255));
+  void* bws = (unsigned char*)m_dev + 256;
+  const TickHdr* th = (const TickHdr*)tick_buf;
+  const TickEntry* ent = (const TickEntry*)((const unsigned char*)tick_buf + sizeof(TickHdr));
+  const uint32_t blocks = (max_entries + 255) / 256;
+  hipLaunchKernelGGL(k_tick_expand, dim3(blocks), dim3(256), 0, s, th, ent, slots, keys, ctr0s, lens, offs, kinds,
+                     m_dev, max_entries);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  BatchDesc d{keys, ctr0s, lens, offs, kinds, max_entries, arena, arena_bytes};
+  return launch_batch_body(d, m_dev, bws, cfg, s);
+}
+
 struct TickLane {
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
@@ -123,6 +222,7 @@ struct sq_server {
   sq_launch_cfg lcfg{};
   int device = 0;
   unsigned char* arena_dev = nullptr;
+  SlotDev* slots_dev = nullptr;       // max_slots request descriptions, written by the ticks
   std::vector<TickLane> lanes;
 
   std::mutex mu;
@@ -131,6 +231,7 @@ struct sq_server {
   std::unordered_map<uint64_t, Req> reqs;
   std::vector<uint64_t> active;       // admitted, not complete, in admission order
   size_t rr = 0;                      // round-robin start in `active` for ticks under a byte cap
+  std::vector<uint32_t> free_slots;
   std::unordered_set<uint64_t> cancelled;
   Arena* arena = nullptr;
   uint64_t next_id = 1;
@@ -145,7 +246,7 @@ struct sq_server {
   void loop();
   bool retire_locked();
   bool admit_locked();
-  TickLane* build_tick_locked();
+  bool build_tick_locked(TickLane* L);
   void finish_locked(Req& r);
 };
 
@@ -157,6 +258,7 @@ void sq_server::finish_locked(Req& r) {
   outputs += r.n;
   bytes_done += r.bytes;
   last_complete = r.t_done;
+  free_slots.push_back(r.slot);
   active.erase(std::find(active.begin(), active.end(), r.id));
   if (r.flags & SQ_SERVE_DISCARD) {
     arena->release(r.off, r.bytes);
@@ -179,6 +281,7 @@ bool sq_server::retire_locked() {
     any = true;
     for (uint64_t id : L.reqs) {
       Req& r = reqs.at(id);
+      r.slot_ready = true;
       if (--r.inflight == 0 && r.next == r.n) finish_locked(r);
     }
     L.reqs.clear();
@@ -190,12 +293,14 @@ bool sq_server::retire_locked() {
 // the arena has room.
 bool sq_server::admit_locked() {
   bool any = false;
-  while (!queue.empty() && active.size() < cfg.max_slots) {
+  while (!queue.empty() && !free_slots.empty()) {
     Req& r = reqs.at(queue.front());
     uint64_t off = 0;
     if (!arena->alloc(r.bytes, &off)) break;  // head of line waits for room
     queue.pop_front();
     r.off = off;
+    r.slot = free_slots.back();
+    free_slots.pop_back();
     r.st = St::Active;
     active.push_back(r.id);
     ++admitted;
@@ -204,15 +309,10 @@ bool sq_server::admit_locked() {
   return any;
 }
 
-// Fills an idle lane's pinned tick buffer with the next chunk of every
-// admitted request that has outputs left; returns the lane, or nullptr if
-// no lane is idle or nothing is left to schedule.  The launch itself happens
-// outside the lock.
-TickLane* sq_server::build_tick_locked() {
-  TickLane* L = nullptr;
-  for (auto& l : lanes)
-    if (!l.busy) { L = &l; break; }
-  if (L == nullptr) return nullptr;
+// Fills idle lane L's pinned tick buffer with the next chunk of admitted
+// requests that have outputs left; returns false (L stays idle) if there
+// are none.  The launch itself happens outside the lock.
+bool sq_server::build_tick_locked(TickLane* L) {
   TickHdr* th_ = (TickHdr*)L->host_buf;
   TickEntry* ent = (TickEntry*)(L->host_buf + sizeof(TickHdr));
   uint32_t m = 0;
@@ -221,13 +321,18 @@ TickLane* sq_server::build_tick_locked() {
   auto add = [&](Req& r) {
     const uint64_t cnt = std::min<uint64_t>(cfg.chunk_cap, r.n - r.next);
     const uint32_t W = (uint32_t)kind_bytes(r.kind);
-    ent[m].key = r.key;
-    // split kinds: chunks start at an even output, the low word of a pair
-    ent[m].ctr0 = r.ctr0 + (r.kind == SQ_U32X2 || r.kind == SQ_F32X2 ? r.next >> 1 : r.next);
-    ent[m].count = cnt;
-    ent[m].out_off = r.off + r.next * W;
-    ent[m].kind = (uint32_t)r.kind;
-    ent[m].pad = 0;
+    TickEntry& te = ent[m];
+    te = TickEntry{};
+    te.slot = r.slot;
+    te.first = r.next;
+    te.count = cnt;
+    if (!r.slot_ready) {  // the slot may not be written yet: carry the description
+      te.init = 1;
+      te.key = r.key;
+      te.ctr0 = r.ctr0;
+      te.out_off = r.off;
+      te.kind = (uint32_t)r.kind;
+    }
     r.next += cnt;
     ++r.inflight;
     L->reqs.push_back(r.id);
@@ -236,24 +341,27 @@ TickLane* sq_server::build_tick_locked() {
   };
   // requests that finish within this chunk first (they leave the tick done),
   // then the others from the round-robin position while under the byte cap
+  auto mine = [](const Req& r) { return r.next < r.n; };
   for (uint64_t id : active) {
     if (m == cfg.max_slots) break;
     Req& r = reqs.at(id);
-    if (r.next < r.n && r.n - r.next <= cfg.chunk_cap) add(r);
+    if (mine(r) && r.n - r.next <= cfg.chunk_cap) add(r);
   }
-  const size_t na = active.size();
+  // each request at most once per tick: one pass over `active` from a fixed
+  // start (a slot must not appear twice in a tick)
+  const size_t na = active.size(), start = rr;
   for (size_t k = 0; k < na && m < cfg.max_slots && (bytes < cap || m == 0); ++k) {
-    const size_t i = (rr + k) % na;
+    const size_t i = (start + k) % na;
     Req& r = reqs.at(active[i]);
-    if (r.next >= r.n) continue;
+    if (!mine(r)) continue;
     add(r);
     rr = i + 1;
   }
-  if (m == 0) return nullptr;
+  if (m == 0) return false;
   th_->entries = m;
   L->busy = true;
   ++ticks;
-  return L;
+  return true;
 }
 
 // The scheduler.  Lane state (busy, finished, event status) belongs to this
@@ -277,7 +385,8 @@ void sq_server::loop() {
       std::unique_lock<std::mutex> lk(mu);
       progress |= retire_locked();
       progress |= admit_locked();
-      while (TickLane* L = build_tick_locked()) to_launch.push_back(L);
+      for (auto& L : lanes)
+        if (!L.busy && build_tick_locked(&L)) to_launch.push_back(&L);
       inflight = std::any_of(lanes.begin(), lanes.end(), [](const TickLane& l) { return l.busy; });
       if (stop && !inflight && active.empty() && queue.empty()) exit_now = true;
       else if (!inflight && !progress) cv_work.wait_for(lk, std::chrono::milliseconds(20));
@@ -310,6 +419,7 @@ static void server_free(sq_server* s) {
     if (L.host_buf) (void)hipHostFree(L.host_buf);
     if (L.ws) (void)hipFree(L.ws);
   }
+  if (s->slots_dev) (void)hipFree(s->slots_dev);
   if (s->arena_dev) (void)hipFree(s->arena_dev);
   delete s->arena;
   delete s;
@@ -336,6 +446,7 @@ int sq_server_create(const sq_server_cfg* cfg, sq_server** out) {
   if (cfg->tile_log2) s->lcfg.tile_log2 = cfg->tile_log2;
   s->arena = new Arena(cfg->hbm_budget_bytes);
   hipError_t e = hipMalloc((void**)&s->arena_dev, cfg->hbm_budget_bytes);
+  if (e == hipSuccess) e = hipMalloc((void**)&s->slots_dev, sizeof(SlotDev) * cfg->max_slots);
   s->lanes.resize(cfg->n_streams);
   const size_t tbuf = sizeof(TickHdr) + sizeof(TickEntry) * (size_t)cfg->max_slots;
   for (auto& L : s->lanes) {
@@ -349,8 +460,8 @@ int sq_server_create(const sq_server_cfg* cfg, sq_server** out) {
     // capture expand -> scan -> fill once over this lane's fixed buffers
     e = hipStreamBeginCapture(L.stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-      hipError_t le = launch_tick(L.host_buf, cfg->max_slots, s->arena_dev, cfg->hbm_budget_bytes, L.ws, s->lcfg,
-                                  L.stream);
+      hipError_t le = launch_tick(L.host_buf, s->slots_dev, cfg->max_slots, s->arena_dev, cfg->hbm_budget_bytes,
+                                  L.ws, s->lcfg, L.stream);
       hipError_t ee = hipStreamEndCapture(L.stream, &L.graph);
       e = le != hipSuccess ? le : ee;
     }
@@ -361,6 +472,7 @@ int sq_server_create(const sq_server_cfg* cfg, sq_server** out) {
     server_free(s);
     return r;
   }
+  for (uint32_t i = 0; i < cfg->max_slots; ++i) s->free_slots.push_back(cfg->max_slots - 1 - i);
   s->th = std::thread([s] { s->loop(); });
   *out = s;
   return SQ_OK;

@@ -69,6 +69,33 @@ def test_server_alone_equals_mix_equals_oracle(sq, oracle_mod, n_streams, chunk_
         assert st["arena_used_bytes"] == 0 and st["active_now"] == 0
 
 
+K1, K2, K3 = 0x6C8E9CF570932BD5, 0x3F1E5D7C9B2A4069, 0x1234567890ABCDEF
+
+
+@pytest.mark.parametrize("reqs,n_streams", [
+    ([(0, K1, 0, 20000), (0, K2, 100, 20000)], 1),
+    ([(0, K1, 0, 20000), (0, K2, 100, 5)], 1),
+    ([(0, K1, 0, 5), (0, K2, 100, 20000)], 1),
+    ([(0, K1, 0, 20000), (3, K2, 2**64 - 3000, 20000), (4, K3, 7, 9001)], 1),
+    ([(0, K1, 0, 20000), (0, K2, 100, 20000), (5, K3, 2**64 - 1, 12345)], 2),
+])
+def test_server_multi_chunk_requests_share_ticks(sq, oracle_mod, reqs, n_streams):
+    """Several multi-chunk requests in the same ticks: each request's state
+    lives in its device slot and is advanced once per tick (a request takes
+    at most one chunk of a tick), so every output matches the oracle."""
+    log(f"server multi-chunk {[(q[0], q[3]) for q in reqs]} n_streams={n_streams}")
+    with sq.Server(64 << 20, max_slots=64, chunk_cap=4096, n_streams=n_streams) as srv:
+        ids = [srv.submit(*q) for q in reqs]
+        for rid in ids:
+            srv.wait(rid)
+        for q, rid in zip(reqs, ids):
+            got = to_host_bytes(srv.result_bytes(rid))
+            exp = _oracle(oracle_mod, *q)
+            assert got.tobytes() == exp.tobytes(), (q, first_diff(got, exp))
+        # one chunk per request per tick: at least as many ticks as the longest request has chunks
+        assert srv.stats()["ticks"] >= max(-(-q[3] // 4096) for q in reqs)
+
+
 def test_server_admission_by_budget_queues(sq, oracle_mod):
     """More requests than the arena holds at once: later ones wait in the
     queue until earlier outputs are released, then complete correctly."""
