@@ -89,7 +89,6 @@ static int load_file(const char* path) {
   FILE* f = std::fopen(path, "r");
   if (!f) return fail(SQ_ENOTFOUND, std::string("cannot open tuning table ") + path);
   char line[512];
-  int loaded = 0;
   std::vector<std::pair<int, Entry>> rows;
   int op, kind, bucket;
   unsigned block, unroll, gpc, xcd, tile;
@@ -102,7 +101,6 @@ static int load_file(const char* path) {
       sq_launch_cfg c{block, unroll, gpc, xcd, tile};
       if (!cfg_valid((sq_op)op, c)) continue;
       rows.push_back({(op * kKinds + kind) * kBuckets + bucket, Entry{c, true}});
-      ++loaded;
     }
   }
   std::fclose(f);
