@@ -155,8 +155,12 @@ int sq_tune_save(const char *path);
  * scratch buffers of up to `max_bytes` bytes that it allocates itself (this
  * call is not on the hot path), keeps only candidates whose output is
  * bit-identical to the default configuration's, and stores the fastest in
- * the table.  op_mask bit i selects sq_op i.  Writes the table to
- * `save_path` when non-null.  Synchronous. */
+ * the table.  Fill candidates are timed both right after a compute-bound
+ * kernel (a fused sum over 2^31 counters) and back to back, and scored by
+ * the sum of the two medians (the shader clock a fill meets depends on what
+ * ran before it); reduce and batch candidates back to back.  op_mask bit i
+ * selects sq_op i.  Writes the table to `save_path` when non-null.
+ * Synchronous. */
 int sq_autotune(uint32_t op_mask, uint64_t max_bytes, const char *save_path);
 
 /* ------------------------------------------------------------------------
