@@ -526,13 +526,16 @@ __device__ __forceinline__ TileDesc tile_desc(const sqi::BatchDesc& d, uint32_t 
   const bool split = r.kind > 3;  // two elements per counter; tiles hold an even count
   r.key = d.keys[s];
   r.ctr = d.ctr0s[s] + (split ? off >> 1 : off);
-  r.p = d.out + d.offs[s] + off * ((r.kind == 2 || r.kind == 3) ? 8u : 4u);
+  const uint64_t pos = d.offs[s] + off * ((r.kind == 2 || r.kind == 3) ? 8u : 4u);  // byte offset in the arena
   // the same tile for every lane: keep its description in scalar registers
   // so the tile's setup and loop control run on the scalar unit
   r.key = wave_uniform(r.key);
   r.ctr = wave_uniform(r.ctr);
   r.cnt = wave_uniform(r.cnt);
-  r.p = (unsigned char*)wave_uniform((uint64_t)r.p);
+  // the byte offset, not the pointer, goes through readfirstlane, so the
+  // pointer stays derived from the kernel argument and the stores remain
+  // global_store (not flat_store)
+  r.p = d.out + wave_uniform(pos);
   r.kind = __builtin_amdgcn_readfirstlane(r.kind);
   return r;
 }
