@@ -2,7 +2,7 @@
 
 Requests (kind, key, ctr0, size) come from the seeded serving trace: sizes
 log-uniform in [2^10, 2^28] outputs, 70% 32-bit (U32/F32) and 30% 64-bit
-(U64/F64), Poisson arrivals.  The driver submits each request at its
+(U64/F64), Poisson arrivals.  The load generator submits each request at its
 scheduled arrival time (busy-waiting in between) with the discard flag, so
 the server frees its output as soon as it completes; latency is measured by
 the server from submit to completion, so it includes queueing.
@@ -40,7 +40,7 @@ def saturated(sq, trace: W.ServeTrace, budget: int, chunk_cap: int, n_streams: i
 def open_loop(sq, trace: W.ServeTrace, budget: int, chunk_cap: int, warmup: int, n_streams: int = 4) -> dict:
     """Submits request i at trace.arrival_s[i] (busy-waiting in between), every
     request with the discard flag; the first `warmup` requests are also kept
-    out of the server's latency statistics.  The driver does nothing but
+    out of the server's latency statistics.  The load generator does nothing but
     submit, so it keeps to the schedule; the server measures each latency
     from submit() to completion."""
     lag_max = 0.0
