@@ -96,6 +96,31 @@ def test_server_multi_chunk_requests_share_ticks(sq, oracle_mod, reqs, n_streams
         assert srv.stats()["ticks"] >= max(-(-q[3] // 4096) for q in reqs)
 
 
+@pytest.mark.parametrize("n_streams,max_slots,chunk_cap", [(4, 4, 4096), (3, 16, 8192), (4, 64, 1 << 16)])
+def test_server_slot_reuse_stress(sq, oracle_mod, n_streams, max_slots, chunk_cap):
+    """Hundreds of requests of every kind through few slots on several lanes:
+    each device slot is reused many times, by requests whose chunks run on
+    different lanes; every output equals the oracle."""
+    rng = np.random.default_rng(1000 + max_slots)
+    reqs = []
+    for i in range(400):
+        kind = int(rng.integers(0, 6))
+        n = int(2 ** rng.uniform(0, 16))
+        ctr0 = int(rng.integers(0, 2**64, dtype=np.uint64)) if i % 3 else 2**64 - int(rng.integers(1, 70000))
+        reqs.append((kind, int(rng.integers(0, 2**64, dtype=np.uint64)), ctr0, n))
+    log(f"server stress n_streams={n_streams} max_slots={max_slots} chunk_cap={chunk_cap}")
+    with sq.Server(64 << 20, max_slots=max_slots, chunk_cap=chunk_cap, n_streams=n_streams) as srv:
+        ids = [srv.submit(*q) for q in reqs]
+        for q, rid in zip(reqs, ids):
+            srv.wait(rid)
+            got = to_host_bytes(srv.result_bytes(rid))
+            exp = _oracle(oracle_mod, *q)
+            assert got.tobytes() == exp.tobytes(), (q, first_diff(got, exp))
+            srv.release(rid)
+        st = srv.stats()
+        assert st["completed"] == len(reqs) == st["released"]
+
+
 def test_server_admission_by_budget_queues(sq, oracle_mod):
     """More requests than the arena holds at once: later ones wait in the
     queue until earlier outputs are released, then complete correctly."""
