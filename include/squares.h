@@ -321,9 +321,11 @@ int sq_batch_plan_destroy(sq_batch_plan *plan);
  *    in arrival order while free slots and HBM budget allow (the request's
  *    output is carved from a device arena of hbm_budget_bytes owned by the
  *    server), so requests are admitted while others are running.
- *  - Each tick is one launch of the batch kernel over the next chunk (at
- *    most chunk_cap outputs) of every admitted, unfinished request; up to
- *    n_streams ticks run concurrently on separate streams.
+ *  - Each tick is one replay of the batch kernels over the next chunk (at
+ *    most chunk_cap outputs) of admitted, unfinished requests, each request
+ *    at most once per tick; up to n_streams ticks run concurrently on
+ *    separate streams, so consecutive chunks of one request may run at
+ *    once on different streams.
  *  - A request's outputs are identical to sq_fill(kind, key, ctr0, n) no
  *    matter what else runs with it.
  *  - Latency = completion seen by the scheduler minus submit() time.
