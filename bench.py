@@ -19,7 +19,7 @@ ragged-batch speedup over per-stream launches and serving latency
 percentiles.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--log2n 32] [--no-extras]
-                       [--extras concurrent,uniform,split,modes,batch,serving] [--no-cpu]
+                       [--extras concurrent,uniform,pair,split,modes,batch,serving] [--no-cpu]
 """
 from __future__ import annotations
 
@@ -49,6 +49,7 @@ SLOTS = {
     "sq64": 5 * 3.0 + 0.5 + 1.0,           # 16.5 (+ the xor of round 5)
     "sum_f32": 0.5 + 1.0,                  # >> 8, 64-bit accumulate
     "sum_f64": 1.0 + 1.0,                  # 64-bit >> 11, 64-bit accumulate
+    "pair_f32": 0.5 + 0.5,                 # the paired sum's F32 term: >> 40, 32-bit accumulate
 }
 KERNEL_SOURCES = ["paper_2004_06278_amd/csrc/sq_device.hpp", "paper_2004_06278_amd/csrc/sq_kernels.hip"]
 # rocprofv3 kernel names (spaces and namespace removed) of the four step
@@ -107,9 +108,9 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--log2n", type=int, default=32)
     p.add_argument("--no-extras", action="store_true")
-    p.add_argument("--extras", default="concurrent,uniform,split,modes,batch,serving",
+    p.add_argument("--extras", default="concurrent,uniform,pair,split,modes,batch,serving",
                    help="comma list of extra measurements after the step "
-                        "(concurrent, uniform, split, modes, batch, serving)")
+                        "(concurrent, uniform, pair, split, modes, batch, serving)")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--calib-copy", action="store_true",
                    help="run a plain 4 GiB device copy first (scales HBM byte counters)")
@@ -200,6 +201,25 @@ def batch_speedup(sq, torch) -> dict:
             "graph_gnum_s": round(n / t_plan / 1e9, 1), "per_stream_gnum_s": round(n / t_each / 1e9, 1),
             "speedup": round(t_each / t_plan, 2), "graph_gb_s": round(4 * n / t_plan / 1e9, 1),
             "misaligned_graph_ms": round(t_mis * 1e3, 3)}
+
+
+def paired_sums(sq, torch, key: int, ctr0: int, n: int, steady_ms: dict) -> dict:
+    """The F32 and F64 sums of the step in one pass (sq_reduce_pair: one
+    squares64 per counter gives both terms, squares32 being its high word),
+    back to back (mean of 10 after 3), against the two separate sums back
+    to back; the results are checked against the separate sums."""
+    r32, r64, ws = sq.result_tensor(), sq.result_tensor(), sq.reduce_workspace(n)
+    ms = _event_ms(torch, lambda: sq.reduce_pair_async(sq.F32, key, ctr0, n, r32, r64, ws), reps=10, warm=3)
+    (s32, _, _), (s64, _, _) = sq.read_result(r32), sq.read_result(r64)
+    assert (s32, s64) == (sq.reduce(sq.F32, key, ctr0, n)[0], sq.reduce(sq.F64, key, ctr0, n)[0])
+    separate = steady_ms["fused_f32_sum"] + steady_ms["fused_f64_sum"]
+    slots = SLOTS["sq64"] + SLOTS["sum_f64"] + SLOTS["pair_f32"]
+    rate = slots * n / (ms * 1e-3)
+    return {"ms": round(ms, 4), "sums_gnum_s": round(2 * n / (ms * 1e-3) / 1e9, 1),
+            "separate_sums_ms": round(separate, 4), "vs_separate": round(separate / ms, 3),
+            "roofline": {"bound": "alu", "achieved": round(rate / 1e12, 3), "peak": round(ALU_PEAK_SLOTS / 1e12, 3),
+                         "unit": "T VALU-slot/s", "frac": round(rate / ALU_PEAK_SLOTS, 4),
+                         "slots_per_counter": slots}}
 
 
 def split_words(sq, torch, key: int, ctr0: int, n: int, per_op_ms: dict) -> dict:
@@ -498,6 +518,8 @@ def main() -> int:
         line["concurrent_step"] = concurrent_step(sq, torch, key, ctr0, n, ms_per_step)
     if "uniform" in extras:
         line["uniform_fills"] = uniform_fills(sq, torch, key, ctr0, n)
+    if "pair" in extras:
+        line["paired_sums"] = paired_sums(sq, torch, key, ctr0, n, steady_ms)
     if "split" in extras:
         line["split_words"] = split_words(sq, torch, key, ctr0, n, per_op_ms)
     if "modes" in extras:

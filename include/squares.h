@@ -193,6 +193,24 @@ int sq_reduce(sq_kind kind, uint64_t key, uint64_t ctr0, uint64_t n, sq_sum_resu
 int sq_reduce_cfg(sq_kind kind, uint64_t key, uint64_t ctr0, uint64_t n, sq_sum_result *out,
                   void *ws, size_t ws_bytes, const sq_launch_cfg *cfg, void *stream);
 
+/* Paired sums: the 32-bit and the 64-bit sum over the same counters in one
+ * pass.  squares32 at a counter is the high word of squares64 at it (both
+ * compute round 4's t = x*x + z; squares32 returns the high word of t,
+ * squares64 keeps t and XORs a value below 2^32 into its low word; Sections
+ * 2 and 5), so one squares64 evaluation per counter gives both terms.
+ * kind32 = SQ_F32: out32 = sq_reduce(SQ_F32, ...) and out64 =
+ * sq_reduce(SQ_F64, ...) over [ctr0, ctr0 + n); kind32 = SQ_U32: the U32 and
+ * U64 sums.  Bit-identical to the two separate calls.  `ws` as for
+ * sq_reduce (sq_reduce_workspace_bytes(n) bytes, 16-byte aligned); out32
+ * and out64 are distinct 8-byte aligned device results.  Errors: SQ_EINVAL
+ * (other kinds, null or equal results, invalid cfg: queue order only,
+ * xcd_map 1), SQ_EALIGN, SQ_ENOMEM (workspace too small), SQ_EHIP. */
+int sq_reduce_pair(sq_kind kind32, uint64_t key, uint64_t ctr0, uint64_t n, sq_sum_result *out32,
+                   sq_sum_result *out64, void *ws, size_t ws_bytes, void *stream);
+int sq_reduce_pair_cfg(sq_kind kind32, uint64_t key, uint64_t ctr0, uint64_t n, sq_sum_result *out32,
+                       sq_sum_result *out64, void *ws, size_t ws_bytes, const sq_launch_cfg *cfg,
+                       void *stream);
+
 /* ------------------------------------------------------------------------
  * Counter increments other than one (Section 4 lists tests of such
  * increments).  Element i is the output of `kind` at counter

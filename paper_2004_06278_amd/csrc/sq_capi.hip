@@ -282,6 +282,33 @@ int sq_reduce(sq_kind kind, uint64_t key, uint64_t ctr0, uint64_t n, sq_sum_resu
   return sq_reduce_cfg(kind, key, ctr0, n, out, ws, ws_bytes, &cfg, stream);
 }
 
+// ---------------------------------------------------------------- paired sums
+int sq_reduce_pair_cfg(sq_kind kind32, uint64_t key, uint64_t ctr0, uint64_t n, sq_sum_result* out32,
+                       sq_sum_result* out64, void* ws, size_t ws_bytes, const sq_launch_cfg* cfg, void* stream) {
+  if (kind32 != SQ_U32 && kind32 != SQ_F32)
+    return fail(SQ_EINVAL, "sq_reduce_pair takes SQ_U32 (paired with SQ_U64) or SQ_F32 (paired with SQ_F64), not " +
+                               std::to_string((int)kind32));
+  if (out32 == nullptr || out64 == nullptr || ws == nullptr) return fail(SQ_EINVAL, "null result or workspace pointer");
+  if (out32 == out64) return fail(SQ_EINVAL, "the two results must be distinct");
+  if (((uintptr_t)out32 & 7) != 0 || ((uintptr_t)out64 & 7) != 0 || ((uintptr_t)ws & 15) != 0)
+    return fail(SQ_EALIGN, "results must be 8-byte and workspace 16-byte aligned");
+  if (ws_bytes < sq_reduce_workspace_bytes(n))
+    return fail(SQ_ENOMEM, "reduce workspace smaller than sq_reduce_workspace_bytes()");
+  if (cfg == nullptr || !cfg_valid(SQ_OP_REDUCE, *cfg) || cfg->xcd_map != 1)
+    return fail(SQ_EINVAL, "invalid paired reduce launch configuration (queue order, xcd_map 1)");
+  SQ_INIT_OR_RETURN();
+  hipError_t e = launch_reduce_pair(kind32, key, ctr0, n, out32, out64, ws, *cfg, (hipStream_t)stream);
+  return e == hipSuccess ? SQ_OK : fail_hip(e, "paired reduce launch");
+}
+
+int sq_reduce_pair(sq_kind kind32, uint64_t key, uint64_t ctr0, uint64_t n, sq_sum_result* out32,
+                   sq_sum_result* out64, void* ws, size_t ws_bytes, void* stream) {
+  // the fused reduce's default shape: 256 lanes, 2 counters per unrolled
+  // step, up to 8 resident workgroups per CU, chunks of 256 x 2^8 counters
+  const sq_launch_cfg cfg{256, 2, 8, 1, 8};
+  return sq_reduce_pair_cfg(kind32, key, ctr0, n, out32, out64, ws, ws_bytes, &cfg, stream);
+}
+
 // ---------------------------------------------------------------- batch
 size_t sq_batch_workspace_bytes(uint32_t m, uint64_t out_bytes) { return batch_ws_bytes(m, out_bytes); }
 

@@ -66,6 +66,11 @@ hipError_t launch_fill(int kind, uint64_t key, uint64_t ctr0, uint64_t n, void* 
 constexpr uint32_t kReduceMaxParts = 65536;
 hipError_t launch_reduce(int kind, uint64_t key, uint64_t ctr0, uint64_t n, sq_sum_result* out,
                          void* ws, const sq_launch_cfg& cfg, hipStream_t s, uint64_t step = 1);
+// Both sums of a pair over the same counters (kind32 SQ_U32 with SQ_U64, or
+// SQ_F32 with SQ_F64) from one squares64 evaluation per counter; unit
+// counter increments, queue order with chunks of 256 x 2^cfg.tile_log2.
+hipError_t launch_reduce_pair(int kind32, uint64_t key, uint64_t ctr0, uint64_t n, sq_sum_result* out32,
+                              sq_sum_result* out64, void* ws, const sq_launch_cfg& cfg, hipStream_t s);
 
 // Key-counter mode: out[j] = kind's output at counter ctr under keys[j].
 hipError_t launch_keys(int kind, uint64_t ctr, const uint64_t* keys, uint64_t m, void* out,

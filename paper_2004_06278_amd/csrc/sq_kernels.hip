@@ -333,6 +333,96 @@ __global__ __launch_bounds__(256) void k_reduce_queue(ReduceArgs a) {
   }
 }
 
+// ============================================================== paired sums
+// The 32-bit and the 64-bit sum over the same counters from one squares64
+// evaluation per counter: squares32 at a counter is the high word of
+// squares64 at it (both compute round 4's value t = x*x + z; squares32
+// returns its high word, squares64 keeps t whole and XORs a value below 2^32
+// into its low word).  P = 1: the F32 and F64 sums; P = 0: the U32 and U64
+// sums.
+template <int P>
+__device__ __forceinline__ void pair_terms(uint64_t v, typename std::conditional<P == 1, uint32_t, uint64_t>::type& s32,
+                                           uint64_t& s64, uint32_t& carries) {
+  if constexpr (P == 1) {
+    s32 += (uint32_t)(v >> 40);  // squares32 >> 8
+    s64 += v >> 11;
+  } else {
+    s32 += v >> 32;
+    unsigned long long c;
+    s64 = __builtin_addcll(s64, v, 0ull, &c);
+    carries += (uint32_t)c;
+  }
+}
+
+template <int P, int U>
+__device__ __forceinline__ void run_sum_pair(uint64_t y, uint64_t cnt, uint64_t key, uint64_t& lo32,
+                                             uint64_t& hi32, uint64_t& lo64, uint64_t& hi64) {
+  // F32 terms < 2^24: 256 fit a 32-bit partial; F64 terms < 2^53: 256 fit
+  // 64 bits.  U32 terms < 2^32: 2^20 fit 64 bits; U64 terms count carries.
+  constexpr uint32_t FLUSH = P == 1 ? 256u : (1u << 20);
+  typedef typename std::conditional<P == 1, uint32_t, uint64_t>::type Part32;
+  uint64_t i = 0;
+  while (i < cnt) {
+    const uint32_t len = (uint32_t)(cnt - i < FLUSH ? cnt - i : FLUSH);
+    Part32 s32 = 0;
+    uint64_t s64 = 0;
+    uint32_t carries = 0;
+    uint32_t j = 0;
+    for (; j + U <= len; j += U) {
+      y = opaque(y);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint64_t z = y + key;
+        pair_terms<P>(sq64(y, z), s32, s64, carries);
+        y = z;
+      }
+    }
+    for (; j < len; ++j) {
+      const uint64_t z = y + key;
+      pair_terms<P>(sq64(y, z), s32, s64, carries);
+      y = z;
+    }
+    add128(lo32, hi32, (uint64_t)s32, 0);
+    add128(lo64, hi64, s64, carries);
+    i += len;
+  }
+}
+
+// Queue order as k_reduce_queue (unit counter increments); the 32-bit sum's
+// partials go to a.partials, the 64-bit sum's to partials64.
+template <int P, int U>
+__global__ __launch_bounds__(256) void k_reduce_pair_queue(ReduceArgs a, uint64_t* partials64) {
+  __shared__ uint64_t s_chunk;
+  const uint64_t chunk = (uint64_t)blockDim.x * a.per;
+  uint64_t lo32 = 0, hi32 = 0, lo64 = 0, hi64 = 0;
+#pragma unroll 1
+  while (true) {
+    if (threadIdx.x == 0) s_chunk = atomicAdd(a.next, 1ull);
+    __syncthreads();
+    const uint64_t c = wave_uniform(s_chunk);
+    __syncthreads();
+    if (c >= a.nchunks) break;
+    const uint64_t begin = c * chunk + (uint64_t)threadIdx.x * a.per;
+    if ((c + 1) * chunk <= a.n) {
+      run_sum_pair<P, U>(a.y0 + begin * a.key, a.per, a.key, lo32, hi32, lo64, hi64);
+    } else {
+      const uint64_t cnt = begin < a.n ? (a.n - begin < a.per ? a.n - begin : a.per) : 0;
+      run_sum_pair<P, U>(a.y0 + begin * a.key, cnt, a.key, lo32, hi32, lo64, hi64);
+    }
+  }
+  block_sum128(lo32, hi32);
+  if (threadIdx.x == 0) {
+    a.partials[2 * blockIdx.x] = lo32;
+    a.partials[2 * blockIdx.x + 1] = hi32;
+  }
+  __syncthreads();  // thread 0 has read the first combine's LDS before it is reused
+  block_sum128(lo64, hi64);
+  if (threadIdx.x == 0) {
+    partials64[2 * blockIdx.x] = lo64;
+    partials64[2 * blockIdx.x + 1] = hi64;
+  }
+}
+
 __global__ void k_reduce_reset(unsigned long long* next) {
   if (threadIdx.x == 0) *next = 0;
 }
@@ -868,6 +958,44 @@ hipError_t launch_reduce(int kind, uint64_t key, uint64_t ctr0, uint64_t n, sq_s
   const uint64_t y_tail = (ctr0 + units * step) * key;
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, (const uint64_t*)ws, (uint32_t)grid, n, scale,
                      split_tail, y_tail, key, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_pair(int kind32, uint64_t key, uint64_t ctr0, uint64_t n, sq_sum_result* out32,
+                              sq_sum_result* out64, void* ws, const sq_launch_cfg& cfg, hipStream_t s) {
+  const uint32_t B = 256;
+  typedef void (*PairKernel)(ReduceArgs, uint64_t*);
+  const bool f = kind32 == SQ_F32;
+  PairKernel k = cfg.unroll == 1 ? (f ? k_reduce_pair_queue<1, 1> : k_reduce_pair_queue<0, 1>)
+               : cfg.unroll == 2 ? (f ? k_reduce_pair_queue<1, 2> : k_reduce_pair_queue<0, 2>)
+                                 : (f ? k_reduce_pair_queue<1, 4> : k_reduce_pair_queue<0, 4>);
+  const uint32_t gpc = std::min<uint32_t>(cfg.grid_per_cu, (uint32_t)resident_blocks((const void*)k, B));
+  uint64_t grid = (uint64_t)device_info().cus * gpc;
+  ReduceArgs a{};
+  a.key = key;
+  a.ctr0 = ctr0;
+  a.n = n;
+  a.dkey = key;
+  a.y0 = ctr0 * key;
+  a.per = 1ull << cfg.tile_log2;
+  const uint64_t chunk = (uint64_t)B * a.per;
+  a.nchunks = n / chunk + (n % chunk != 0);
+  if (grid > a.nchunks) grid = a.nchunks ? a.nchunks : 1;
+  if (grid > kReduceMaxParts / 2) grid = kReduceMaxParts / 2;  // both partial arrays before the queue counter
+  a.ythread = a.per * a.dkey;
+  a.partials = (uint64_t*)ws;
+  uint64_t* partials64 = (uint64_t*)ws + 2 * grid;
+  a.next = (unsigned long long*)((unsigned char*)ws + 16ull * kReduceMaxParts);
+  hipLaunchKernelGGL(k_reduce_reset, dim3(1), dim3(64), 0, s, a.next);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3((uint32_t)grid), dim3(B), 0, s, a, partials64);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, (const uint64_t*)ws, (uint32_t)grid, n, f ? -24 : 0,
+                     0, 0ull, key, out32);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, (const uint64_t*)partials64, (uint32_t)grid, n,
+                     f ? -53 : 0, 0, 0ull, key, out64);
   return hipGetLastError();
 }
 

@@ -86,6 +86,9 @@ SIGNATURES = {
     "sq_reduce_workspace_bytes": (ctypes.c_size_t, [_u64]),
     "sq_reduce": (_int, [_int, _u64, _u64, _u64, _vp, _vp, ctypes.c_size_t, _vp]),
     "sq_reduce_cfg": (_int, [_int, _u64, _u64, _u64, _vp, _vp, ctypes.c_size_t, ctypes.POINTER(LaunchCfg), _vp]),
+    "sq_reduce_pair": (_int, [_int, _u64, _u64, _u64, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "sq_reduce_pair_cfg": (_int, [_int, _u64, _u64, _u64, _vp, _vp, _vp, ctypes.c_size_t,
+                                  ctypes.POINTER(LaunchCfg), _vp]),
     "sq32_at": (_int, [_u64, _u64, ctypes.POINTER(_u32)]),
     "sq64_at": (_int, [_u64, _u64, ctypes.POINTER(_u64)]),
     "sq_u128_to_double_scaled": (ctypes.c_double, [_u64, _u64, _int]),
@@ -362,6 +365,27 @@ def reduce(kind: int, key: int, ctr0: int, n: int, launch_cfg: LaunchCfg | None 
     ws = reduce_workspace(n)
     reduce_async(kind, key, ctr0, n, res, ws, launch_cfg=launch_cfg)
     return read_result(res)
+
+
+def reduce_pair_async(kind32: int, key: int, ctr0: int, n: int, result32, result64, ws, stream=None,
+                      launch_cfg: LaunchCfg | None = None) -> None:
+    """Launches the paired sum (kind32 U32 with U64, or F32 with F64) into two
+    32-byte CUDA result tensors."""
+    _out(result32, 32, _torch().uint8)
+    _out(result64, 32, _torch().uint8)
+    args = (kind32, key & M64, ctr0 & M64, n, _ptr(result32), _ptr(result64), _ptr(ws), ws.numel() * ws.element_size())
+    if launch_cfg is None:
+        check(lib().sq_reduce_pair(*args, _stream(stream)))
+    else:
+        check(lib().sq_reduce_pair_cfg(*args, ctypes.byref(launch_cfg), _stream(stream)))
+
+
+def reduce_pair(kind32: int, key: int, ctr0: int, n: int, launch_cfg: LaunchCfg | None = None):
+    """((sum32, value32, n), (sum64, value64, n)) of the paired sum."""
+    r32, r64 = result_tensor(), result_tensor()
+    ws = reduce_workspace(n)
+    reduce_pair_async(kind32, key, ctr0, n, r32, r64, ws, launch_cfg=launch_cfg)
+    return read_result(r32), read_result(r64)
 
 
 # ---------------------------------------------------------------- batch

@@ -104,6 +104,24 @@ def test_reduce_argument_checks():
     assert _rc(L.sq_reduce_cfg, 1, 1, 0, 10, FAKE, FAKE, need, squares.LaunchCfg(256, 4, 8, 2, 16), None)[0] == -1
 
 
+def test_reduce_pair_argument_checks():
+    from paper_2004_06278_amd import squares
+
+    L = squares.lib()
+    need = L.sq_reduce_workspace_bytes(1 << 20)
+    F2 = FAKE + 4096
+    for kind32 in (2, 3, 4, 5, 9):  # only U32 (with U64) and F32 (with F64)
+        assert _rc(L.sq_reduce_pair, kind32, 1, 0, 10, FAKE, F2, FAKE, need, None)[0] == -1
+    assert _rc(L.sq_reduce_pair, 1, 1, 0, 10, None, F2, FAKE, need, None)[0] == -1
+    assert _rc(L.sq_reduce_pair, 1, 1, 0, 10, FAKE, None, FAKE, need, None)[0] == -1
+    assert _rc(L.sq_reduce_pair, 1, 1, 0, 10, FAKE, FAKE, F2, need, None)[0] == -1   # same result twice
+    assert _rc(L.sq_reduce_pair, 1, 1, 0, 10, FAKE + 4, F2, FAKE, need, None)[0] == -2
+    assert _rc(L.sq_reduce_pair, 1, 1, 0, 10, FAKE, F2, FAKE + 8, need, None)[0] == -2
+    assert _rc(L.sq_reduce_pair, 1, 1, 0, 10, FAKE, F2, FAKE, need - 16, None)[0] == -3
+    static = squares.LaunchCfg(256, 2, 8, 0, 16)  # the paired sum has the queue order only
+    assert _rc(L.sq_reduce_pair_cfg, 1, 1, 0, 10, FAKE, F2, FAKE, need, static, None)[0] == -1
+
+
 def test_mode_argument_checks():
     """Strided fill and sum, key-counter mode and key generation reject bad
     arguments before any device work."""

@@ -116,3 +116,54 @@ def test_reduce_rejects_bad_workspace(sq):
     with pytest.raises(sq.SquaresError) as e:
         sq.reduce_async(9, 1, 0, 100, res, sq.reduce_workspace())
     assert e.value.status == -1
+
+
+# ---------------------------------------------------------------- paired sums
+@pytest.mark.parametrize("kind32", [0, 1])
+def test_reduce_pair_small_and_ragged(sq, oracle_mod, kind32):
+    """The paired sum (U32+U64 or F32+F64 from one squares64 per counter)
+    equals the oracle's two separate exact sums, which evaluate squares32
+    and squares64 independently."""
+    kind64 = kind32 + 2
+    g = np.random.Generator(np.random.PCG64(300 + kind32))
+    for n in [0, 1, 2, 63, 255, 256, 257, 1000, 65536 + 3, (1 << 20) + 1, (1 << 22) + 11]:
+        key = int(g.integers(0, 2**64, dtype=np.uint64))
+        ctr0 = 2**64 - int(g.integers(1, 1 << 21)) if n % 2 else int(g.integers(0, 2**64, dtype=np.uint64))
+        log(f"reduce pair kind32={kind32} n={n} key={key:#x} ctr0={ctr0:#x}")
+        (s32, v32, n32), (s64, v64, n64) = sq.reduce_pair(kind32, key, ctr0, n)
+        ref32 = oracle_mod.exact_sum(kind32, key, ctr0, n, threads=HOST_THREADS)
+        ref64 = oracle_mod.exact_sum(kind64, key, ctr0, n, threads=HOST_THREADS)
+        assert (s32, s64) == (ref32, ref64), n
+        assert v32 == oracle_mod.rounded_value(kind32, ref32) and v64 == oracle_mod.rounded_value(kind64, ref64)
+        assert n32 == n64 == n
+
+
+@pytest.mark.parametrize("kind32", [0, 1])
+def test_reduce_pair_every_config_and_keys(sq, oracle_mod, kind32):
+    n = (1 << 21) + 77
+    kind64 = kind32 + 2
+    for key in (0, 1, 2**63, 0x9E3779B97F4A7C15):
+        ctr0 = 2**64 - 1000
+        ref32 = oracle_mod.exact_sum(kind32, key, ctr0, n, threads=HOST_THREADS)
+        ref64 = oracle_mod.exact_sum(kind64, key, ctr0, n, threads=HOST_THREADS)
+        for u in (1, 2, 4):
+            for gpc in (1, 8):
+                for pl in (6, 8, 12):
+                    c = sq.cfg(block=256, unroll=u, grid_per_cu=gpc, xcd_map=1, tile_log2=pl)
+                    log(f"reduce pair kind32={kind32} key={key:#x} cfg={c.as_dict()}")
+                    (s32, _, _), (s64, _, _) = sq.reduce_pair(kind32, key, ctr0, n, launch_cfg=c)
+                    assert (s32, s64) == (ref32, ref64), (key, c.as_dict())
+
+
+def test_reduce_pair_full_size_equals_separate_sums(sq, oracle_mod):
+    """The single-key workload (n = 2^32): the paired F32+F64 sum equals the
+    oracle's exact sums."""
+    from paper_2004_06278_amd import workloads as W
+
+    c = W.single_key_case()
+    n = 1 << 32
+    log(f"full-size reduce pair key={c.key:#x} ctr0={c.ctr0:#x}")
+    (s32, v32, _), (s64, v64, _) = sq.reduce_pair(1, c.key, c.ctr0, n)
+    assert s32 == oracle_mod.exact_sum(1, c.key, c.ctr0, n, threads=HOST_THREADS)
+    assert s64 == oracle_mod.exact_sum(3, c.key, c.ctr0, n, threads=HOST_THREADS)
+    assert v32 == oracle_mod.rounded_value(1, s32) and v64 == oracle_mod.rounded_value(3, s64)
