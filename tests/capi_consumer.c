@@ -71,6 +71,17 @@ int main(void)
     CHECK(hres.lo == ref[0] && hres.hi == ref[1] && hres.n == n, "sq_reduce equals the oracle's exact sum");
     CHECK(sq_u128_to_double_scaled(ref[0], ref[1], -53) == hres.value, "nearest-even value");
 
+    /* both widths in one pass (F32 and F64 sums) */
+    sq_sum_result *dres2 = NULL, h32res, h64res;
+    HIP(hipMalloc((void **)&dres2, 2 * sizeof *dres2));
+    CHECK(sq_reduce_pair(SQ_F32, key, ctr0, n, dres2, dres2 + 1, ws, wsb, NULL) == SQ_OK, "sq_reduce_pair");
+    HIP(hipMemcpy(&h32res, dres2, sizeof h32res, hipMemcpyDeviceToHost));
+    HIP(hipMemcpy(&h64res, dres2 + 1, sizeof h64res, hipMemcpyDeviceToHost));
+    uint64_t ref32[2];
+    oracle_sum(1, key, ctr0, n, ref32);
+    CHECK(h32res.lo == ref32[0] && h32res.hi == ref32[1], "paired F32 sum equals the oracle");
+    CHECK(h64res.lo == ref[0] && h64res.hi == ref[1] && h64res.value == hres.value, "paired F64 sum equals sq_reduce");
+
     /* ragged batch: three streams of different kinds in one arena */
     const uint32_t m = 3;
     uint64_t keys[3] = {key, key + 2, 0x1234567890ABCDEFull};
@@ -107,13 +118,13 @@ int main(void)
     CHECK(strlen(sq_last_error()) > 0, "error message set");
     CHECK(sq32_fill(key, ctr0, 10, (uint32_t *)((char *)d32 + 2), NULL) == SQ_EALIGN, "misaligned output rejected");
 
-    hipFree(d32); hipFree(df); hipFree(ws); hipFree(dres); hipFree(dk); hipFree(dc); hipFree(dl);
+    hipFree(d32); hipFree(df); hipFree(ws); hipFree(dres); hipFree(dres2); hipFree(dk); hipFree(dc); hipFree(dl);
     hipFree(doff); hipFree(dkind); hipFree(dout); hipFree(bws);
     free(h32); free(r32); free(hf); free(rf); free(hb); free(rb);
     if (failures) {
         fprintf(stderr, "%d check(s) failed\n", failures);
         return 1;
     }
-    printf("capi consumer: fill, uniform, reduce, batch and error paths match the oracle\n");
+    printf("capi consumer: fill, uniform, reduce, paired reduce, batch and error paths match the oracle\n");
     return 0;
 }
