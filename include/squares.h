@@ -347,6 +347,10 @@ int sq_batch_plan_destroy(sq_batch_plan *plan);
  *  - A request's outputs are identical to sq_fill(kind, key, ctr0, n) no
  *    matter what else runs with it.
  *  - Latency = completion seen by the scheduler minus submit() time.
+ *  - The scheduler is one host thread per server; while ticks are in flight
+ *    it polls their completion events (yielding between polls) for the
+ *    lowest latency, so it keeps one host core busy; when idle it sleeps on
+ *    a condition variable.
  * ------------------------------------------------------------------------ */
 typedef struct sq_server sq_server;
 
