@@ -207,7 +207,8 @@ def paired_sums(sq, torch, key: int, ctr0: int, n: int, steady_ms: dict) -> dict
     """The F32 and F64 sums of the step in one pass (sq_reduce_pair: one
     squares64 per counter gives both terms, squares32 being its high word),
     back to back (mean of 10 after 3), against the two separate sums back
-    to back; the results are checked against the separate sums."""
+    to back; the results are checked against the separate sums.  Also the
+    step with its two sums taken as one paired pass (10 steps after 3)."""
     r32, r64, ws = sq.result_tensor(), sq.result_tensor(), sq.reduce_workspace(n)
     ms = _event_ms(torch, lambda: sq.reduce_pair_async(sq.F32, key, ctr0, n, r32, r64, ws), reps=10, warm=3)
     (s32, _, _), (s64, _, _) = sq.read_result(r32), sq.read_result(r64)
@@ -215,8 +216,30 @@ def paired_sums(sq, torch, key: int, ctr0: int, n: int, steady_ms: dict) -> dict
     separate = steady_ms["fused_f32_sum"] + steady_ms["fused_f64_sum"]
     slots = SLOTS["sq64"] + SLOTS["sum_f64"] + SLOTS["pair_f32"]
     rate = slots * n / (ms * 1e-3)
+    # the step with the two sums taken as one paired pass (the headline step
+    # keeps the separate calls)
+    out32 = torch.empty(n, dtype=torch.uint32, device="cuda")
+    out64 = torch.empty(n, dtype=torch.uint64, device="cuda")
+
+    def step():
+        sq.fill(sq.U32, key, ctr0, n, out=out32)
+        sq.fill(sq.U64, key, ctr0, n, out=out64)
+        sq.reduce_pair_async(sq.F32, key, ctr0, n, r32, r64, ws)
+
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        step()
+    torch.cuda.synchronize()
+    step_ms = (time.perf_counter() - t0) * 1e3 / 10
+    del out32, out64
+    torch.cuda.empty_cache()
     return {"ms": round(ms, 4), "sums_gnum_s": round(2 * n / (ms * 1e-3) / 1e9, 1),
             "separate_sums_ms": round(separate, 4), "vs_separate": round(separate / ms, 3),
+            "step_with_paired_sums_ms": round(step_ms, 4),
+            "step_with_paired_sums_gnum_s": round(4 * n / (step_ms * 1e-3) / 1e9, 1),
             "roofline": {"bound": "alu", "achieved": round(rate / 1e12, 3), "peak": round(ALU_PEAK_SLOTS / 1e12, 3),
                          "unit": "T VALU-slot/s", "frac": round(rate / ALU_PEAK_SLOTS, 4),
                          "slots_per_counter": slots}}
