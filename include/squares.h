@@ -359,7 +359,8 @@ typedef struct {
                                    output lives here until released */
     uint32_t max_slots;         /* requests admitted and not yet complete (also the most
                                    chunks in one tick), 1..65536 */
-    uint64_t chunk_cap;         /* outputs of one request per tick (>= 4096) */
+    uint64_t chunk_cap;         /* outputs of one request per tick (>= 4096; rounded down to
+                                   an even count so that split-kind chunks start at a low word) */
     uint32_t n_streams;         /* concurrent ticks (one HIP stream each), 1..8.  HIP binds
                                    a stream to one of a few hardware queues (4 per process
                                    by default) when it first runs work; in a process whose
