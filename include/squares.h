@@ -339,7 +339,7 @@ int sq_batch_plan_destroy(sq_batch_plan *plan);
  *    in arrival order while free slots and HBM budget allow (the request's
  *    output is carved from a device arena of hbm_budget_bytes owned by the
  *    server), so requests are admitted while others are running.
- *  - Each tick is one replay of the batch kernels over the next chunk (at
+ *  - Each tick is one run of the batch kernels over the next chunk (at
  *    most chunk_cap outputs) of admitted, unfinished requests, each request
  *    at most once per tick; up to n_streams ticks run concurrently on
  *    separate streams, so consecutive chunks of one request may run at
