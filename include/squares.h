@@ -351,6 +351,10 @@ int sq_batch_plan_destroy(sq_batch_plan *plan);
  *    it polls their completion events (yielding between polls) for the
  *    lowest latency, so it keeps one host core busy; when idle it sleeps on
  *    a condition variable.
+ *  - Errors: if a tick's launch or its completion event reports a HIP
+ *    error, the server starts no further tick; submit, poll, wait, result
+ *    and latency then return SQ_EHIP (the message names the error), and
+ *    destroy frees the server without waiting for the unfinished requests.
  * ------------------------------------------------------------------------ */
 typedef struct sq_server sq_server;
 
@@ -406,7 +410,8 @@ int sq_server_release(sq_server *srv, uint64_t req_id);
 /* Cancels a request that is still queued (SQ_EBUSY once admitted). */
 int sq_server_cancel(sq_server *srv, uint64_t req_id);
 int sq_server_stats(sq_server *srv, sq_server_stats_t *out);
-/* Drains admitted work, then frees the server and its arena. */
+/* Drains admitted work (unless a HIP error stopped the server), then frees the
+ * server and its arena; returns SQ_EHIP if the server had failed. */
 int sq_server_destroy(sq_server *srv);
 
 #ifdef __cplusplus

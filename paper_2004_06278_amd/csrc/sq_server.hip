@@ -385,10 +385,12 @@ void sq_server::loop() {
       std::unique_lock<std::mutex> lk(mu);
       progress |= retire_locked();
       progress |= admit_locked();
+      // after a HIP error no further tick starts: the admitted requests stay
+      // incomplete and every call reports the error
       for (auto& L : lanes)
-        if (!L.busy && build_tick_locked(&L)) to_launch.push_back(&L);
+        if (fatal.empty() && !L.busy && build_tick_locked(&L)) to_launch.push_back(&L);
       inflight = std::any_of(lanes.begin(), lanes.end(), [](const TickLane& l) { return l.busy; });
-      if (stop && !inflight && active.empty() && queue.empty()) exit_now = true;
+      if (stop && !inflight && ((active.empty() && queue.empty()) || !fatal.empty())) exit_now = true;
       else if (!inflight && !progress) cv_work.wait_for(lk, std::chrono::milliseconds(20));
     }
     if (exit_now) break;
@@ -526,6 +528,7 @@ int sq_server_wait(sq_server* s, uint64_t id) {
 int sq_server_result(sq_server* s, uint64_t id, void** ptr, uint64_t* bytes) {
   if (s == nullptr || ptr == nullptr || bytes == nullptr) return fail(SQ_EINVAL, "null argument");
   std::lock_guard<std::mutex> g(s->mu);
+  if (!s->fatal.empty()) return fail(SQ_EHIP, "server failed: " + s->fatal);
   auto it = s->reqs.find(id);
   if (it == s->reqs.end()) return fail(SQ_ENOTFOUND, "unknown, released or discarded request");
   if (it->second.st != St::Done) return fail(SQ_EBUSY, "request not complete");
@@ -537,6 +540,7 @@ int sq_server_result(sq_server* s, uint64_t id, void** ptr, uint64_t* bytes) {
 int sq_server_latency(sq_server* s, uint64_t id, double* seconds) {
   if (s == nullptr || seconds == nullptr) return fail(SQ_EINVAL, "null argument");
   std::lock_guard<std::mutex> g(s->mu);
+  if (!s->fatal.empty()) return fail(SQ_EHIP, "server failed: " + s->fatal);
   auto it = s->reqs.find(id);
   if (it == s->reqs.end()) return fail(SQ_ENOTFOUND, "unknown, released or discarded request");
   if (it->second.st != St::Done) return fail(SQ_EBUSY, "request not complete");
