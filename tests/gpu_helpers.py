@@ -19,6 +19,8 @@ def oracle_element(o, kind: int, key: int, ctr0: int, i: int) -> bytes:
         pair = o.fill(kind, key, (ctr0 + i // 2) % 2**64, 2).view(np.uint8)
         return pair[4 * (i & 1): 4 * (i & 1) + 4].tobytes()
     return o.fill(kind, key, (ctr0 + i) % 2**64, 1).view(np.uint8).tobytes()
+
+
 HOST_THREADS = max(1, min(16, os.cpu_count() or 1))
 
 

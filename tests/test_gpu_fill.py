@@ -193,6 +193,37 @@ def test_full_size_sampled(sq, oracle_mod, kind):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("kind", [0, 4])
+def test_fill_past_2p32_outputs(sq, oracle_mod, kind):
+    """n = 2^32 + 2^17 + 3 outputs (16 GiB): output indices past 32 bits and
+    byte offsets past 2^34.  The 2^16 outputs before index 2^32 and the whole
+    ragged tail after it equal the oracle's, as do 2^12 random positions; the
+    counter passes 2^64 - 1 -> 0 inside the tail."""
+    import torch
+
+    from paper_2004_06278_amd import workloads as W
+
+    key = W.single_key_case().key
+    n = (1 << 32) + (1 << 17) + 3
+    per_ctr = 2 if kind in (4, 5) else 1            # outputs per counter
+    wrap_at = (1 << 32) + 100                       # output index whose counter is 0
+    ctr0 = (2**64 - wrap_at // per_ctr) % 2**64
+    log(f"fill past 2^32 outputs kind={kind} key={key:#x} ctr0={ctr0:#x} n={n}")
+    out = sq.fill(kind, key, ctr0, n)
+    start = (1 << 32) - (1 << 16)                   # even: a split pair starts here
+    got = to_host_bytes(out.view(torch.uint8)[start * 4: n * 4])
+    want = oracle_bytes(oracle_mod, kind, key, (ctr0 + start // per_ctr) % 2**64, n - start)
+    assert np.array_equal(got, want), first_diff(got, want)
+    g = np.random.Generator(np.random.PCG64(57 + kind))
+    idx = g.integers(0, n, size=1 << 12)
+    iv = out.view(torch.int32)
+    got = iv[torch.from_numpy(idx.astype(np.int64)).cuda()].cpu().numpy().view(np.uint8).reshape(-1, 4)
+    for row, i in zip(got, idx):
+        assert row.tobytes() == oracle_element(oracle_mod, kind, key, ctr0, int(i)), f"position {int(i)}"
+    del out, iv
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("kind", [0, 1, 2, 3])
 def test_full_size_complete(sq, oracle_mod, kind):
     """Every one of the n = 2^32 outputs of the single-key workload (U32 and

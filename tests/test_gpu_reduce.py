@@ -97,6 +97,42 @@ def test_reduce_full_size_exact(sq, oracle_mod, kind):
     assert abs(v / n - 0.5) < 1e-4
 
 
+@pytest.mark.parametrize("kind", [1, 2, 4])
+def test_reduce_past_2p32_counters(sq, oracle_mod, kind):
+    """Sums over more than 2^32 counters (chunk and thread offsets past 32
+    bits), ragged, with the counter passing 2^64 - 1 -> 0 near the end: equal
+    to the oracle's exact sum.  The split kind sums 2^33 + 2^21 + 12345
+    outputs (an odd count: the last counter's low word only)."""
+    from paper_2004_06278_amd import workloads as W
+
+    key = W.single_key_case().key
+    counters = (1 << 32) + (1 << 20) + 12345
+    n = 2 * counters - 1 if kind in (4, 5) else counters
+    ctr0 = 2**64 - counters + 1000
+    log(f"reduce past 2^32 counters kind={kind} key={key:#x} ctr0={ctr0:#x} n={n}")
+    s, v, nn = sq.reduce(kind, key, ctr0, n)
+    ref = oracle_mod.exact_sum(kind, key, ctr0, n, threads=HOST_THREADS)
+    assert s == ref
+    assert v == oracle_mod.rounded_value(kind, ref)
+    assert nn == n
+
+
+def test_reduce_pair_past_2p32_counters(sq, oracle_mod):
+    """The paired F32 + F64 sums over 2^32 + 2^20 + 12345 counters equal the
+    oracle's two exact sums."""
+    from paper_2004_06278_amd import workloads as W
+
+    key = W.single_key_case().key
+    n = (1 << 32) + (1 << 20) + 12345
+    ctr0 = 2**64 - n + 1000
+    log(f"paired reduce past 2^32 counters key={key:#x} ctr0={ctr0:#x} n={n}")
+    (s32, v32, _), (s64, v64, _) = sq.reduce_pair(1, key, ctr0, n)
+    r32 = oracle_mod.exact_sum(1, key, ctr0, n, threads=HOST_THREADS)
+    r64 = oracle_mod.exact_sum(3, key, ctr0, n, threads=HOST_THREADS)
+    assert (s32, s64) == (r32, r64)
+    assert (v32, v64) == (oracle_mod.rounded_value(1, r32), oracle_mod.rounded_value(3, r64))
+
+
 def test_reduce_u64_carries(sq, oracle_mod):
     """A U64 sum over 2^24 outputs exceeds 2^64: the high word must carry."""
     key, ctr0, n = 0xC3A5C85C97CB3127, 99, 1 << 24
