@@ -5,7 +5,7 @@ from __future__ import annotations
 import numpy as np
 import pytest
 
-from gpu_helpers import KIND_BYTES, compare_batch_arena, first_diff, log, to_host_bytes
+from gpu_helpers import HOST_THREADS, KIND_BYTES, compare_batch_arena, first_diff, log, to_host_bytes
 
 pytestmark = pytest.mark.gpu
 
@@ -66,6 +66,50 @@ def test_batch_equals_per_stream_fills(sq):
         alone = sq.fill(k, int(b.keys[s]), int(b.ctr0s[s]), L)
         assert to_host_bytes(alone).tobytes() == arena[off: off + L * KIND_BYTES[k]].tobytes(), s
     torch.cuda.synchronize()
+
+
+def test_batch_stream_past_2p32_outputs(sq, oracle_mod):
+    """A batch whose middle stream holds 2^32 + 3 * 2^14 + 7 U32 outputs (16
+    GiB: tile offsets inside the stream past 32 bits; its counter wraps 200
+    outputs after index 2^32) between a short F32 stream at a misaligned
+    start and a short F64 stream: the short streams whole, the big stream's
+    outputs from index 2^32 - 2^16 to its end and 2^12 random positions of it
+    equal the oracle's."""
+    import torch
+
+    from paper_2004_06278_amd import workloads as W
+
+    big = (1 << 32) + 3 * (1 << 14) + 7
+    keys = np.array([0x1234567890ABCDEF, W.single_key_case().key, 0xFEDCBA0987654321], dtype=np.uint64)
+    ctr0s = np.array([5, 2**64 - (1 << 32) - 200, 2**64 - 3], dtype=np.uint64)
+    lens = np.array([1001, big, 4099], dtype=np.uint64)
+    kinds = np.array([1, 0, 3], dtype=np.uint8)
+    o0 = 4
+    o1 = o0 + 1001 * 4
+    o2 = (o1 + big * 4 + 7) & ~7
+    offs = np.array([o0, o1, o2], dtype=np.uint64)
+    arena_bytes = o2 + 4099 * 8
+    log(f"batch with a stream past 2^32 outputs: lens={lens.tolist()} offs={offs.tolist()}")
+    db = sq.batch_to_device(keys, ctr0s, lens, offs, kinds, arena_bytes)
+    sq.fill_batch(db)
+    assert sq.batch_errors(db) == 0
+    got0 = to_host_bytes(db.out[o0: o0 + 1001 * 4])
+    assert np.array_equal(got0, oracle_mod.fill(1, int(keys[0]), 5, 1001).view(np.uint8))
+    got2 = to_host_bytes(db.out[o2: o2 + 4099 * 8])
+    assert np.array_equal(got2, oracle_mod.fill(3, int(keys[2]), 2**64 - 3, 4099).view(np.uint8))
+    start = (1 << 32) - (1 << 16)
+    tail = to_host_bytes(db.out[o1 + start * 4: o1 + big * 4])
+    want = oracle_mod.fill(0, int(keys[1]), (int(ctr0s[1]) + start) % 2**64, big - start,
+                           threads=HOST_THREADS).view(np.uint8)
+    assert np.array_equal(tail, want), first_diff(tail, want)
+    g = np.random.Generator(np.random.PCG64(91))
+    idx = g.integers(0, big, size=1 << 12)
+    iv = db.out[o1: o1 + big * 4].view(torch.int32)
+    got = iv[torch.from_numpy(idx.astype(np.int64)).cuda()].cpu().numpy().view(np.uint32)
+    for v, i in zip(got, idx):
+        assert v == oracle_mod.fill(0, int(keys[1]), (int(ctr0s[1]) + int(i)) % 2**64, 1)[0], f"position {int(i)}"
+    del db, iv
+    torch.cuda.empty_cache()
 
 
 def test_batch_invalid_descriptors_skipped(sq, oracle_mod):

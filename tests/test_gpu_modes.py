@@ -265,6 +265,30 @@ def test_make_keys_feed_key_counter_mode(sq, oracle_mod):
 
 
 # ---------------------------------------------------------------- scalar entry points
+def test_make_keys_and_key_counter_past_2p32(sq, oracle_mod):
+    """2^32 + 5 keys generated on the device (32 GiB; key indices past 32 bits,
+    the generator's counter wrapping 500 keys before the end) and a U32
+    key-counter fill over all of them (16 GiB): the last 2^12 keys and
+    outputs and 2^12 random ones equal the oracle's."""
+    import torch
+
+    gk, c0, ctr = 0x243F6A8885A308D3, 2**64 - 2**33 + 1000, 7
+    m = (1 << 32) + 5
+    log(f"make_keys + key-counter past 2^32 gk={gk:#x} c0={c0:#x} m={m}")
+    keys = sq.make_keys(gk, c0, m)
+    out = sq.fill_keys(0, ctr, keys)
+    g = np.random.Generator(np.random.PCG64(77))
+    idx = np.unique(np.concatenate([m - 1 - np.arange(1 << 12), g.integers(0, m, size=1 << 12)])).astype(np.int64)
+    ti = torch.from_numpy(idx).cuda()
+    got_k = keys.view(torch.int64)[ti].cpu().numpy().view(np.uint64)
+    got_o = out.view(torch.int32)[ti].cpu().numpy().view(np.uint32)
+    for j, kj in zip(idx, got_k):
+        assert kj == oracle_mod.make_keys(gk, (c0 + 2 * int(j)) % 2**64, 1)[0], f"key {int(j)}"
+    assert np.array_equal(got_o, oracle_mod.fill_keys(0, ctr, got_k))
+    del keys, out
+    torch.cuda.empty_cache()
+
+
 def test_scalar_entry_points_paper_argument_order(sq, oracle_mod):
     """sq32_at / sq64_at take (ctr, key) like the paper's functions and agree
     with the oracle and with element 0 of a bulk fill called as (key, ctr0)."""
