@@ -134,10 +134,12 @@ def lib() -> ctypes.CDLL:
             if not os.path.exists(LIB_PATH):
                 raise RuntimeError(f"{LIB_PATH} is missing: build it first (__graft_entry__.build())")
             L = ctypes.CDLL(LIB_PATH)
+            missing = [name for name in SIGNATURES if getattr(L, name, None) is None]
+            if missing:
+                raise RuntimeError(f"{LIB_PATH} does not export {', '.join(missing)}: rebuild it "
+                                   "(__graft_entry__.build())")
             for name, (res, args) in SIGNATURES.items():
-                fn = getattr(L, name, None)
-                if fn is None:
-                    continue
+                fn = getattr(L, name)
                 fn.restype = res
                 fn.argtypes = args
             if os.path.exists(TUNE_TABLE) and not os.environ.get("SQ_TUNE_CACHE"):
