@@ -1,8 +1,9 @@
 """Driver of the library's autotuner (sq_autotune).
 
 Runs the tuner for fill, reduce and batch on the current GPU and writes the
-table as JSON.  The library loads `tune_gfx950.json` next to it at start-up
-(or the file named by $SQ_TUNE_CACHE).
+table as JSON.  The Python binding loads `tune_gfx950.json` (next to the
+library) when it first loads the library, unless $SQ_TUNE_CACHE names another
+table, which the library then loads itself; a C program calls sq_tune_load.
 
     python -m paper_2004_06278_amd.autotune [--out PATH] [--max-gib 64]
 """
