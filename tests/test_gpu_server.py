@@ -169,6 +169,32 @@ def test_server_errors_and_cancel(sq):
         sq.Server(1 << 20, n_streams=0)
 
 
+def test_server_discard_and_no_stats_flags(sq):
+    """SERVE_DISCARD frees a request's output as soon as it completes (poll
+    reports it done, result() no longer finds it, the arena is empty again);
+    SERVE_NO_STATS leaves a request out of the latency statistics."""
+    with sq.Server(64 << 20, max_slots=8, chunk_cap=1 << 16, n_streams=2) as srv:
+        flags = sq.SERVE_DISCARD | sq.SERVE_NO_STATS
+        ids = [srv.submit(k % 4, 77 + k, k << 30, (1 << 18) + k, flags) for k in range(6)]
+        for r in ids:
+            srv.wait(r)
+            assert srv.poll(r)
+            with pytest.raises(sq.SquaresError) as e:
+                srv.result(r)
+            assert e.value.status == -6
+        st = srv.stats()
+        assert st["completed"] == st["released"] == 6
+        assert st["arena_used_bytes"] == 0 and st["active_now"] == 0
+        assert st["p50_s"] == 0 and st["max_s"] == 0          # no latency sample yet
+        kept = srv.submit(0, 5, 0, 1000)
+        srv.wait(kept)
+        st = srv.stats()
+        assert st["max_s"] > 0 and st["p50_s"] == st["max_s"] == srv.latency(kept)
+        assert st["arena_used_bytes"] == 4096                  # 4000 bytes in 256-byte units
+        srv.release(kept)
+        assert srv.stats()["arena_used_bytes"] == 0
+
+
 def test_server_resume_from_saved_counter(sq, oracle_mod):
     """A stream checkpoint is (key, next counter): serving [c, c+a) then
     [c+a, c+a+b) gives the same outputs as serving [c, c+a+b) at once."""
