@@ -369,7 +369,14 @@ bool sq_server::build_tick_locked(TickLane* L) {
 // under `mu`.  HIP calls (event queries, kernel launches) run
 // with the lock released, so submit()/poll() never wait behind them.
 void sq_server::loop() {
-  (void)hipSetDevice(device);
+  // the launch helpers size their grids from this thread's device binding;
+  // without the server's device no tick may start
+  const hipError_t de = hipSetDevice(device);
+  if (de != hipSuccess || ensure_init() != SQ_OK) {
+    std::lock_guard<std::mutex> g(mu);
+    fatal = std::string("scheduler thread cannot bind device ") + std::to_string(device) +
+            (de != hipSuccess ? std::string(": ") + hipGetErrorString(de) : std::string());
+  }
   std::vector<TickLane*> to_launch;
   for (;;) {
     for (auto& L : lanes) {
