@@ -154,7 +154,8 @@ def cpu_baseline(key: int, ctr0: int, log2_sample: int = 31) -> dict:
         pass
     return {"value": round(4 * n / dt / 1e9, 3), "unit": "Gnum/s", "cores": threads, "kind": "oracle",
             "sample": f"2^{log2_sample} counters of each of the 4 step operations (same key and ctr0; fills "
-                      f"into a reused 2^26-element host buffer), {threads} host threads, {dt:.2f} s wall",
+                      f"into a reused 2^26-element host buffer), {threads} host threads, {dt:.2f} s wall, "
+                      f"about {threads * dt:.0f} thread-seconds of CPU work",
             "one_thread_sq32_gnum_s": round(n1 / dt1 / 1e9, 3), "host_cpu": model,
             "host_cpus_visible": os.cpu_count()}
 
