@@ -28,12 +28,23 @@ inline int kind_align(int kind) { return kind == SQ_U32 || kind == SQ_F32 ? 4 : 
 
 // Nearest double (ties to even) of the 128-bit integer (hi:lo) times 2^e:
 // the rounding the reduce applies to its exact sum, on the device in the
-// final reduce kernel and on the host in sq_u128_to_double_scaled.
+// final reduce kernel and on the host in sq_u128_to_double_scaled.  One
+// rounding for every e: the bits dropped are those below the result's last
+// place, which is 52 places under its leading bit, or 2^-1074 where the
+// result is subnormal.
 __host__ __device__ inline double round_scaled(uint64_t lo, uint64_t hi, int e) {
-  if (hi == 0 && lo < (1ull << 53)) return ldexp((double)lo, e);
+  if (hi == 0 && lo < (1ull << 53)) return ldexp((double)lo, e);  // exact, rounded once by ldexp
+  // beyond these bounds every S in [2^53, 2^128) overflows or rounds to 0 alike
+  if (e > 1100) e = 1100;
+  if (e < -1300) e = -1300;
   const int msb = hi ? 127 - __builtin_clzll(hi) : 63 - __builtin_clzll(lo);
-  int s = msb - 52;  // bits dropped, >= 1
+  int s = msb - 52;                  // bits dropped, >= 1
+  if (s + e < -1074) s = -1074 - e;  // subnormal result: its last place is 2^-1074
   const unsigned __int128 S = ((unsigned __int128)hi << 64) | lo;
+  if (s > msb) {  // S * 2^e is below one unit of the last place: that unit or 0
+    const bool up = s == msb + 1 && S > (((unsigned __int128)1) << msb);  // above half; a tie goes to 0 (even)
+    return up ? ldexp(1.0, s + e) : 0.0;
+  }
   uint64_t mant = (uint64_t)(S >> s);
   const unsigned __int128 rem = S & ((((unsigned __int128)1) << s) - 1);
   const unsigned __int128 half = ((unsigned __int128)1) << (s - 1);

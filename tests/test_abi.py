@@ -230,6 +230,38 @@ def test_u128_rounding_helper_matches_oracle(oracle_mod):
             assert squares.u128_to_double_scaled(S, scale) == oracle_mod.rounded_value(kind, S), (S, kind)
 
 
+def test_u128_rounding_helper_every_exponent():
+    """The helper rounds once for any scale, subnormal and overflowing results
+    included: equal to Python's correctly rounded integer division (or
+    product), with ties at the subnormal boundary going to even."""
+    import math
+
+    import numpy as np
+
+    from paper_2004_06278_amd import squares
+
+    def nearest(S, e):
+        try:
+            return float(S * 2**e) if e >= 0 else S / 2**-e
+        except OverflowError:
+            return math.inf
+
+    g = np.random.Generator(np.random.PCG64(78))
+    cases = [1, 3, 2**53 + 1, 2**54 + 2, 2**54 + 6, 2**64 - 1, 2**127 + 2**74, 2**128 - 1]
+    for bits in range(54, 129, 5):
+        cases += [int(v) >> (128 - bits) for v in
+                  (int(g.integers(0, 2**64, dtype=np.uint64)) << 64 | int(g.integers(0, 2**64, dtype=np.uint64))
+                   for _ in range(6))]
+    # exact halves of the smallest subnormal and of subnormal last places
+    cases += [(2 * k + 1) << 70 for k in range(4)] + [3 << 100, 1 << 100, (1 << 100) + 1]
+    exps = [-1400, -1250, -1203, -1202, -1180, -1176, -1175, -1174, -1150, -1130, -1100, -1076, -1075, -1074,
+            -1060, -1023, -1022, -1000, -53, 0, 895, 896, 960, 970, 971, 1000, 1100, 2000]
+    for S in cases:
+        for e in exps:
+            got = squares.u128_to_double_scaled(S, e)
+            assert got == nearest(S, e), (S, e, got, nearest(S, e))
+
+
 def test_tune_table_roundtrip(tmp_path):
     """The tuning table is host state: set, get, save and load without a GPU."""
     from paper_2004_06278_amd import squares
