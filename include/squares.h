@@ -115,8 +115,8 @@ int sq_uniform_f32x2(uint64_t key, uint64_t ctr0, uint64_t n, float *out, void *
  * Launch configurations (chosen by the autotuner; explicit for tests).
  * ------------------------------------------------------------------------ */
 typedef struct {
-    uint32_t block;        /* threads per workgroup: 64, 128, 256, 512 or 1024 (fill);
-                              256, 512 or 1024 (batch); reduce uses 256 */
+    uint32_t block;        /* threads per workgroup: 64, 128, 256, 512 or 1024 (fill and
+                              batch); the reduce ignores it and always uses 256 */
     uint32_t unroll;       /* 16-byte vectors per lane per chunk: 1, 2, 4 or 8 (fill and
                               batch); outputs per lane per step for reduce: 1, 2 or 4 */
     uint32_t grid_per_cu;  /* workgroups per compute unit (grid = CUs * this), 1..64 */
@@ -127,12 +127,13 @@ typedef struct {
                               reduce: 0 static split over a resident grid; 1 the
                               resident grid takes chunks of 256 * 2^tile_log2
                               counters (tile_log2 6..16) from a queue */
-    uint32_t tile_log2;    /* batch only: a tile holds 2^tile_log2 * 4 bytes of output
+    uint32_t tile_log2;    /* batch: a tile holds 2^tile_log2 * 4 bytes of output
                               (2^tile_log2 outputs of 4-byte kinds, half as many of
                               8-byte kinds), 10..24
                               (batch xcd_map: 0 persistent grid, static interleave;
                               1 persistent grid, tiles taken from a queue in order;
-                              2 one tile per workgroup) */
+                              2 one tile per workgroup).  reduce with xcd_map 1: the
+                              queue's chunk size, as above.  fill: unused */
 } sq_launch_cfg;
 
 /* Operation classes the tuning table is keyed by. */
