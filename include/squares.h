@@ -313,8 +313,8 @@ int sq_fill_streams(const uint64_t *keys, const uint64_t *ctr0s, const uint64_t 
  * `stream`). */
 int sq_batch_errors(const void *ws, void *stream, uint32_t *count);
 
-/* Batch plan: the tile scan and the persistent kernel captured once into a
- * HIP graph over fixed descriptor, arena and workspace addresses.  Each
+/* Batch plan: the tile scan, the tile map and the fill kernel captured once
+ * into a HIP graph over fixed descriptor, arena and workspace addresses.  Each
  * launch replays the graph and reads the descriptor arrays' CURRENT
  * contents, so the caller may rewrite keys/ctr0s/lens/offs/kinds (same m)
  * between launches without re-capture. */
