@@ -112,6 +112,29 @@ def test_batch_stream_past_2p32_outputs(sq, oracle_mod):
     torch.cuda.empty_cache()
 
 
+def test_per_stream_launches_equal_oracle_and_batch(sq, oracle_mod):
+    """sq_fill_streams (one fill launch per stream, the batch's baseline)
+    writes the oracle's arena, byte for byte the same as sq_fill_batch, for
+    every kind at misaligned offsets, with empty streams and wrapping
+    counters."""
+    import torch
+
+    from paper_2004_06278_amd import workloads as W
+
+    b = W.small_random_batch(seed=12, m=200, max_len=30000, kinds=(0, 1, 2, 3, 4, 5))
+    ref = _oracle_arena(oracle_mod, b)
+    log(f"per-stream launches m={b.m} arena={b.arena_bytes}")
+    db = sq.batch_to_device(b.keys, b.ctr0s, b.lens, b.offs, b.kinds, b.arena_bytes)
+    sq.fill_streams(b.keys, b.ctr0s, b.lens, b.offs, b.kinds, db.out, b.arena_bytes)
+    streams = to_host_bytes(db.out)[: b.arena_bytes]
+    assert streams.tobytes() == ref.tobytes(), first_diff(streams, ref)
+    db.out.zero_()
+    sq.fill_batch(db)
+    batch = to_host_bytes(db.out)[: b.arena_bytes]
+    assert batch.tobytes() == streams.tobytes(), first_diff(batch, streams)
+    torch.cuda.synchronize()
+
+
 def test_batch_invalid_descriptors_skipped(sq, oracle_mod):
     """Streams with an unknown kind, a misaligned offset or a range past the
     arena are skipped (nothing written) and counted; valid ones are exact."""
