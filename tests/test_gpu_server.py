@@ -8,7 +8,7 @@ import time
 import numpy as np
 import pytest
 
-from gpu_helpers import KIND_BYTES, first_diff, log, to_host_bytes
+from gpu_helpers import KIND_BYTES, first_diff, log, oracle_element, to_host_bytes
 
 pytestmark = pytest.mark.gpu
 
@@ -193,6 +193,52 @@ def test_server_discard_and_no_stats_flags(sq):
         assert st["arena_used_bytes"] == 4096                  # 4000 bytes in 256-byte units
         srv.release(kept)
         assert srv.stats()["arena_used_bytes"] == 0
+
+
+def test_server_full_size_requests_sampled(sq, oracle_mod):
+    """The serving workload at its real sizes, in the benchmark's server
+    configuration (32 GiB budget, 4096 slots, chunks of 2^24 outputs, 4
+    lanes): 60 requests of the serving trace (log-uniform 2^10..2^28 outputs,
+    70% 32-bit) plus two of 2^28 outputs (U32 and U64, the second wrapping its
+    counter), submitted at once.  Requests below 2^20 outputs are compared
+    whole; larger ones on their first and last 2^14 outputs and 512 random
+    positions, each against the oracle."""
+    import torch
+
+    from paper_2004_06278_amd import workloads as W
+
+    tr = W.serve_trace(seed=8, r=60, qps=1e9)
+    reqs = [(int(tr.kinds[i]), int(tr.keys[i]), int(tr.ctr0s[i]), int(tr.sizes[i])) for i in range(60)]
+    reqs += [(0, 0x6C8E9CF570932BD5, 12345, 1 << 28), (2, 0x3F1E5D7C9B2A4069, 2**64 - (1 << 27), 1 << 28)]
+    log(f"server full-size requests: {len(reqs)}, largest {max(q[3] for q in reqs)} outputs")
+    g = np.random.Generator(np.random.PCG64(81))
+    with sq.Server(32 << 30, max_slots=4096, chunk_cap=1 << 24, n_streams=4) as srv:
+        ids = [srv.submit(*q) for q in reqs]
+        for q, rid in zip(reqs, ids):
+            srv.wait(rid)
+            kind, key, ctr0, n = q
+            W_ = KIND_BYTES[kind]
+            out = srv.result_bytes(rid)
+            if n < (1 << 20):
+                got = to_host_bytes(out)
+                exp = _oracle(oracle_mod, kind, key, ctr0, n)
+                assert got.tobytes() == exp.tobytes(), (q, first_diff(got, exp))
+            else:
+                k = 1 << 14
+                head = to_host_bytes(out[: k * W_])
+                tail = to_host_bytes(out[(n - k) * W_:])
+                assert head.tobytes() == _oracle(oracle_mod, kind, key, ctr0, k).tobytes(), q
+                assert tail.tobytes() == _oracle(oracle_mod, kind, key, (ctr0 + n - k) % 2**64, k).tobytes(), q
+                idx = g.integers(0, n, size=512)
+                words = out.view(torch.int32 if W_ == 4 else torch.int64)
+                got = words[torch.from_numpy(idx.astype(np.int64)).cuda()].cpu().numpy().view(np.uint8).reshape(-1, W_)
+                for row, i in zip(got, idx):
+                    assert row.tobytes() == oracle_element(oracle_mod, kind, key, ctr0, int(i)), (q, int(i))
+            del out
+            srv.release(rid)
+        st = srv.stats()
+        assert st["completed"] == len(reqs) == st["released"] and st["arena_used_bytes"] == 0
+    torch.cuda.empty_cache()
 
 
 def test_server_resume_from_saved_counter(sq, oracle_mod):
