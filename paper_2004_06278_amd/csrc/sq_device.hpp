@@ -116,7 +116,15 @@ __device__ __forceinline__ uint64_t sq64(uint64_t y, uint64_t z) {
 // Exact conversions to [0,1): top 24 bits of a squares32 output, top 53 bits
 // of a squares64 output, each scaled by a power of two.
 __device__ __forceinline__ float to_f32(uint32_t u) { return (float)(u >> 8) * 0x1p-24f; }
-__device__ __forceinline__ double to_f64(uint64_t u) { return (double)(u >> 11) * 0x1p-53; }
+// (u >> 11) * 2^-53 in five exact steps: the high word and the low word with
+// its low 11 bits cleared convert exactly, hi * 2^32 + lo has at most 53
+// significant bits (so the fused multiply-add is exact), and scaling by
+// 2^-64 is exact (the result is 0 or at least 2^-53).
+__device__ __forceinline__ double to_f64(uint64_t u) {
+  const double hi = (double)(uint32_t)(u >> 32);
+  const double lo = (double)((uint32_t)u & 0xFFFFF800u);
+  return __builtin_fma(hi, 0x1p32, lo) * 0x1p-64;
+}
 
 // Output-kind traits.  Kind numbering matches sq_kind in squares.h.
 //   W:     bytes per output element
