@@ -49,6 +49,22 @@ __device__ __forceinline__ uint64_t wave_uniform(uint64_t v) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// yc + tid*ekey (mod 2^64) for a wave-uniform yc and ekey: the first Weyl
+// term of the vector lane `tid` owns when consecutive lanes own consecutive
+// vectors.  The high word of tid*ekey's upper part is added to yc first
+// (one 32-bit multiply and add), then one 32x32->64 multiply-add supplies
+// tid times the low word of ekey with its carry.  Written out because LLVM
+// otherwise builds the 64-bit product with an extra multiply-add and
+// register moves, which this per-lane setup cannot afford where a lane
+// computes only one 16-byte vector.
+__device__ __forceinline__ uint64_t lane_weyl(uint64_t yc, uint64_t ekey, uint32_t tid) {
+  const uint32_t hi = (uint32_t)(yc >> 32) + tid * (uint32_t)(ekey >> 32);
+  const uint64_t a = ((uint64_t)hi << 32) | (uint32_t)yc;
+  uint64_t t;
+  asm("v_mad_u64_u32 %0, vcc, %1, %2, %3" : "=&v"(t) : "v"(tid), "s"((uint32_t)ekey), "v"(a) : "vcc");
+  return t;
+}
+
 // The two instruction groups of a round, each pinned with a non-volatile
 // asm statement so that LLVM can schedule them but not rewrite them (with
 // plain C it duplicates the multiply-add, strength-reduces round 1's y*y + y

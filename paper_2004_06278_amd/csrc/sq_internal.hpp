@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/squares.h"
 
@@ -69,6 +70,21 @@ sq_launch_cfg default_cfg(sq_op op, int kind, uint64_t n);
 sq_launch_cfg tuned_cfg(sq_op op, int kind, uint64_t n);  // table lookup (default if unset)
 
 // ---------------------------------------------------------------- launches
+// A fill's aligned body is written by one or more launches ("segments") of
+// at most max_segment_chunks(block) chunks of block * unroll 16-byte
+// vectors, so that chunk indices fit 32 bits and no grid reaches 2^32
+// work-items.  plan_fill is host code (no device needed).
+struct FillSegment {
+  uint64_t first_chunk;  // index of the segment's first chunk in the body
+  uint32_t nchunks;      // chunks in the segment
+  uint32_t full;         // leading chunks that are whole
+  uint32_t rem;          // vectors of the last chunk if it is not whole, else 0
+  uint32_t grid;         // workgroups launched
+  uint32_t xcd_map;      // chunk order actually used (1 falls back to 0 below 8 workgroups)
+};
+uint32_t max_segment_chunks(uint32_t block);
+void plan_fill(uint64_t nvec, const sq_launch_cfg& cfg, uint32_t cus, std::vector<FillSegment>& segs);
+
 // step: counter increment between consecutive outputs (1 for the plain
 // fill and reduce).
 hipError_t launch_fill(int kind, uint64_t key, uint64_t ctr0, uint64_t n, void* out,

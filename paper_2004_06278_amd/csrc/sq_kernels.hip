@@ -16,6 +16,7 @@
 #include <map>
 #include <mutex>
 #include <type_traits>
+#include <vector>
 
 #include "sq_device.hpp"
 #include "sq_internal.hpp"
@@ -25,40 +26,41 @@ using namespace sqd;
 namespace {
 
 // ============================================================== fill
+// One launch covers one segment of the 1 KiB-aligned body: at most
+// max_segment_chunks() chunks, so chunk indices fit 32 bits and a grid of
+// one workgroup per chunk stays below 2^32 work-items.  Larger fills are
+// split into several launches on the same stream.
 struct FillArgs {
   uint64_t key;
-  uint64_t ctr0;        // counter of element 0
-  unsigned char* out;   // address of element 0 (element-aligned)
-  uint64_t nvec;        // full 16-byte vectors in the aligned body
-  uint64_t nchunks;     // ceil(nvec / (block * U))
-  uint64_t full_chunks; // floor(nvec / (block * U))
-  uint64_t step;        // counter increment between consecutive outputs
-  uint64_t dkey;        // step * key: first-Weyl-term increment per counter visited
-  uint64_t y_body;      // first Weyl term of the body: (ctr0 + step * counter offset of head) * key
-  uint64_t ekey;        // CPV * dkey: Weyl step from one vector to the next
-  uint32_t head;        // elements before the 1 KiB aligned body (< 1024 / W)
-  uint32_t tail;        // elements after the last full vector (0..3)
-  uint32_t xcd_map;     // chunk order, see sq_launch_cfg
+  uint64_t ctr0;          // counter of element 0 (head and tail elements)
+  unsigned char* out;     // address of element 0 (element-aligned)
+  unsigned char* body;    // first 16-byte vector of this segment (1 KiB aligned)
+  uint64_t step;          // counter increment between consecutive outputs
+  uint64_t dkey;          // step * key: first-Weyl-term increment per counter visited
+  uint64_t y_body;        // first Weyl term of the segment's first vector
+  uint64_t ekey;          // Weyl step from one vector to the next (CPV * dkey)
+  uint64_t body_nvec;     // full vectors of the whole body (where the tail starts)
+  uint32_t nchunks;       // chunks of B*U vectors in this segment
+  uint32_t full;          // leading chunks of the segment that are whole
+  uint32_t rem;           // vectors of the last chunk when it is not whole
+  uint32_t head;          // elements before the body (< 1024 / W)
+  uint32_t tail;          // elements after the body's last full vector (0..3)
+  uint32_t xcd_map;       // chunk order, see sq_launch_cfg
+  uint32_t edges;         // this launch also writes the head and tail elements
   uint32_t pad;
 };
 
 // Elements before the body (up to the first 1 KiB boundary) and after its
-// last full vector, one element store each, by workgroup 0.
+// last full vector, one element store each, by workgroup 0 of the launch
+// that carries them.
 template <int K>
 __device__ __forceinline__ void fill_edges(const FillArgs& a) {
   constexpr int W = Kind<K>::W, E = 16 / W;
-  if (blockIdx.x != 0) return;
+  if (!a.edges || blockIdx.x != 0) return;
   for (uint32_t t = threadIdx.x; t < a.head + a.tail; t += blockDim.x) {
-    const uint64_t i = t < a.head ? (uint64_t)t : a.head + a.nvec * E + (t - a.head);
+    const uint64_t i = t < a.head ? (uint64_t)t : a.head + a.body_nvec * E + (t - a.head);
     store_elem<K>(a.out + i * W, a.ctr0, i, a.key, a.step);
   }
-}
-
-// c < n for workgroup-uniform values using 32-bit compares, which stay on
-// the scalar unit (gfx950 has no 64-bit scalar less-than).
-__device__ __forceinline__ bool uniform_lt(uint64_t c, uint64_t n) {
-  const uint32_t ch = (uint32_t)(c >> 32), nh = (uint32_t)(n >> 32);
-  return ch < nh || (ch == nh && (uint32_t)c < (uint32_t)n);
 }
 
 // One 16-byte vector of the body: unit counter increments share each
@@ -69,29 +71,22 @@ __device__ __forceinline__ u32x4 body_vec(const FillArgs& a, uint64_t y) {
   else return gen_vec<K>(y, a.key);
 }
 
-// Chunk c covers vectors [c*B*U, (c+1)*B*U) of the body; lane tid writes
-// vectors c*B*U + u*B + tid, u < U (so each store instruction of a wave
-// covers 1 KiB contiguous, and a workgroup's U stores cover B*U*16 bytes).
+// Chunk c of the segment covers vectors [c*B*U, (c+1)*B*U); lane tid writes
+// vectors c*B*U + u*B + tid, u < U, so each store instruction of a wave
+// covers 1 KiB contiguous and a workgroup's U stores cover B*U*16 bytes.
+// y is the lane's first Weyl term for the chunk.  The chunk's base address
+// is workgroup-uniform (scalar registers); the store adds the lane's 32-bit
+// offset, so a vector costs no address arithmetic on the VALU.
 template <int K, int U, bool S>
-__device__ __forceinline__ void fill_chunk(const FillArgs& a, uint64_t c) {
-  constexpr int W = Kind<K>::W;
+__device__ __forceinline__ void fill_chunk(const FillArgs& a, uint32_t c, uint64_t y) {
   const uint32_t B = blockDim.x, tid = threadIdx.x;
-  unsigned char* body = a.out + (uint64_t)a.head * W;
-  // The chunk's first vector and its Weyl term are workgroup-uniform (scalar
-  // registers); each lane adds only its own 32-bit offset.
-  const uint64_t c0 = c * B * U;
-  const uint64_t yc = opaque_uniform(a.y_body + c0 * a.ekey);
-  const uint64_t v0 = c0 + tid;
-  // opaque: otherwise loop-strength reduction keeps a separate induction
-  // variable (two VGPRs each) for every unrolled vector's y
-  uint64_t y = opaque(yc + (uint64_t)tid * a.ekey);
-  const uint64_t step = (uint64_t)B * a.ekey;
-  u32x4* p = (u32x4*)body + c0 + tid;
-  if (uniform_lt(c, a.full_chunks)) {
+  unsigned char* base = a.body + (uint64_t)c * B * U * 16;
+  const uint64_t ystep = (uint64_t)B * a.ekey;
+  if (c < a.full) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      p[(uint64_t)u * B] = body_vec<K, S>(a, y);
-      y += step;
+      *(u32x4*)(base + (uint64_t)u * B * 16 + tid * 16u) = body_vec<K, S>(a, y);
+      y += ystep;
       // one vector's chains at a time: keeps VGPR use low (occupancy hides
       // the latency of the dependent rounds better than interleaving)
       __builtin_amdgcn_sched_barrier(0);
@@ -99,8 +94,8 @@ __device__ __forceinline__ void fill_chunk(const FillArgs& a, uint64_t c) {
   } else {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (v0 + (uint64_t)u * B < a.nvec) p[(uint64_t)u * B] = body_vec<K, S>(a, y);
-      y += step;
+      if (tid + (uint32_t)u * B < a.rem) *(u32x4*)(base + (uint64_t)u * B * 16 + tid * 16u) = body_vec<K, S>(a, y);
+      y += ystep;
       __builtin_amdgcn_sched_barrier(0);
     }
   }
@@ -109,23 +104,32 @@ __device__ __forceinline__ void fill_chunk(const FillArgs& a, uint64_t c) {
 template <int K, int U, bool S>
 __global__ __launch_bounds__(1024) void k_fill(FillArgs a) {
   fill_edges<K>(a);
+  const uint32_t tid = threadIdx.x;
+  const uint64_t cw = (uint64_t)blockDim.x * U * a.ekey;  // Weyl step from one chunk to the next
   if (a.xcd_map == 2) {
     // one chunk per workgroup (grid = nchunks): workgroups retire and the
     // next ones start in dispatch order, so the chip writes one narrow
     // moving window of the output
-    if (blockIdx.x < (uint32_t)a.nchunks) fill_chunk<K, U, S>(a, blockIdx.x);  // nchunks < 2^31 here
-  } else if (a.xcd_map == 0) {
+    const uint32_t c = blockIdx.x;
+    if (c < a.nchunks) fill_chunk<K, U, S>(a, c, lane_weyl(opaque_uniform(a.y_body + c * cw), a.ekey, tid));
+    return;
+  }
+  // persistent grids: the lane's offset tid*ekey is computed once
+  const uint64_t lane_y = lane_weyl(0, a.ekey, tid);
+  if (a.xcd_map == 0) {
 #pragma unroll 1
-    for (uint64_t c = blockIdx.x; c < a.nchunks; c += gridDim.x) fill_chunk<K, U, S>(a, c);
+    for (uint32_t c = blockIdx.x; c < a.nchunks; c += gridDim.x)
+      fill_chunk<K, U, S>(a, c, opaque(opaque_uniform(a.y_body + c * cw) + lane_y));
   } else {
     // Workgroups are dispatched round-robin over the 8 XCDs; give XCD r the
     // r-th contiguous eighth of the chunks (gridDim.x is a multiple of 8).
     const uint32_t r = blockIdx.x & 7u, local = blockIdx.x >> 3, gx = gridDim.x >> 3;
-    const uint64_t per = (a.nchunks + 7) / 8;
-    const uint64_t beg = r * per;
-    const uint64_t end = beg + per < a.nchunks ? beg + per : a.nchunks;
+    const uint32_t per = (a.nchunks + 7) / 8;
+    const uint32_t beg = r * per;
+    const uint32_t end = beg + per < a.nchunks ? beg + per : a.nchunks;
 #pragma unroll 1
-    for (uint64_t c = beg + local; c < end; c += gx) fill_chunk<K, U, S>(a, c);
+    for (uint32_t c = beg + local; c < end; c += gx)
+      fill_chunk<K, U, S>(a, c, opaque(opaque_uniform(a.y_body + c * cw) + lane_y));
   }
 }
 
@@ -546,45 +550,50 @@ __global__ __launch_bounds__(256) void k_batch_map(const sqi::BatchHdr* hdr, con
 }
 
 // The workgroup fills `cnt` outputs of kind K from counter ctr at p
-// (element-aligned): a head up to the next 1 KiB boundary and a tail,
-// element stores, and in between chunks of B*8 16-byte vectors laid out as
-// in the plain fill (each store instruction of a wave covers one aligned KiB).
+// (element-aligned, workgroup-uniform): a head up to the next 1 KiB boundary
+// and a tail, element stores, and in between chunks of B*U 16-byte vectors
+// laid out as in the plain fill (each store instruction of a wave covers one
+// aligned KiB).  A tile holds at most 2^24 outputs, so its vector counts fit
+// 32 bits.  The lane's Weyl offset tid*ekey is computed once per tile; a
+// chunk adds it to the chunk's uniform Weyl term (one 64-bit add) and the
+// stores add the lane's 32-bit offset to the chunk's uniform address.
 // Lanes 0..B-1 of the workgroup take part.
 template <int K, int U>
 __device__ __forceinline__ void fill_range(uint64_t key, uint64_t ctr, uint64_t cnt, unsigned char* p, uint32_t B) {
   constexpr int W = Kind<K>::W, E = 16 / W;
   const uint32_t tid = threadIdx.x;
   const uint32_t mis = (uint32_t)((uintptr_t)p & 1023u);
-  uint64_t head = mis ? (1024u - mis) / W : 0;
-  if (head > cnt) head = cnt;
-  const uint64_t nvec = (cnt - head) / E;
-  const uint64_t tail = cnt - head - nvec * E;
-  for (uint64_t t = tid; t < head + tail; t += B) {
-    const uint64_t i = t < head ? t : head + nvec * E + (t - head);
+  uint32_t head = mis ? (1024u - mis) / W : 0;
+  if (head > cnt) head = (uint32_t)cnt;
+  const uint32_t nvec = (uint32_t)((cnt - head) / E);
+  const uint32_t tail = (uint32_t)(cnt - head - (uint64_t)nvec * E);
+  for (uint32_t t = tid; t < head + tail; t += B) {
+    const uint64_t i = t < head ? t : head + (uint64_t)nvec * E + (t - head);
     store_elem<K>(p + i * W, ctr, i, key);
   }
-  u32x4* body = (u32x4*)(p + head * W);
+  unsigned char* body = p + (uint64_t)head * W;
   const uint64_t ekey = (uint64_t)Kind<K>::CPV * key;
   const uint64_t y_body = (ctr + elem_ctr<K>(head)) * key;  // head is even for split kinds
-  const uint64_t step = (uint64_t)B * ekey;
-  const uint64_t per_chunk = (uint64_t)B * U;
+  const uint64_t lane_y = lane_weyl(0, ekey, tid);
+  const uint64_t ystep = (uint64_t)B * ekey;
+  const uint32_t per_chunk = B * U;
 #pragma unroll 1
-  for (uint64_t c0 = 0; c0 < nvec; c0 += per_chunk) {
-    const uint64_t v0 = c0 + tid;
-    uint64_t y = opaque(y_body + v0 * ekey);
-    u32x4* q = body + v0;
+  for (uint32_t c0 = 0; c0 < nvec; c0 += per_chunk) {
+    uint64_t y = opaque(opaque_uniform(y_body + c0 * ekey) + lane_y);
+    unsigned char* base = body + (uint64_t)c0 * 16;
     if (c0 + per_chunk <= nvec) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        q[(uint64_t)u * B] = gen_vec<K>(y, key);
-        y += step;
+        *(u32x4*)(base + (uint64_t)u * B * 16 + tid * 16u) = gen_vec<K>(y, key);
+        y += ystep;
         __builtin_amdgcn_sched_barrier(0);
       }
     } else {
+      const uint32_t rem = nvec - c0;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        if (v0 + (uint64_t)u * B < nvec) q[(uint64_t)u * B] = gen_vec<K>(y, key);
-        y += step;
+        if (tid + (uint32_t)u * B < rem) *(u32x4*)(base + (uint64_t)u * B * 16 + tid * 16u) = gen_vec<K>(y, key);
+        y += ystep;
         __builtin_amdgcn_sched_barrier(0);
       }
     }
@@ -827,6 +836,41 @@ __global__ __launch_bounds__(256) void k_make_keys(uint64_t gen_key, uint64_t ct
 // ============================================================== launchers
 namespace sqi {
 
+uint32_t max_segment_chunks(uint32_t block) {
+  // chunk indices and the grid stay below 2^31, and grid * block below 2^32
+  return std::min<uint32_t>(0x7FFFFFFFu, 0xFFFFFFFFu / block);
+}
+
+void plan_fill(uint64_t nvec, const sq_launch_cfg& cfg, uint32_t cus, std::vector<FillSegment>& segs) {
+  segs.clear();
+  const uint64_t per_chunk = (uint64_t)cfg.block * cfg.unroll;
+  const uint64_t nchunks = nvec / per_chunk + (nvec % per_chunk != 0);
+  const uint64_t maxc = max_segment_chunks(cfg.block);
+  uint64_t first = 0;
+  do {
+    FillSegment g{};
+    g.first_chunk = first;
+    const uint64_t nc = std::min<uint64_t>(nchunks - first, maxc);
+    const uint64_t vecs = std::min<uint64_t>(nvec - first * per_chunk, nc * per_chunk);
+    g.nchunks = (uint32_t)nc;
+    g.full = (uint32_t)(vecs / per_chunk);
+    g.rem = (uint32_t)(vecs - (uint64_t)g.full * per_chunk);
+    g.xcd_map = cfg.xcd_map;
+    uint64_t grid = (uint64_t)cus * cfg.grid_per_cu;
+    if (grid > nc) grid = nc;
+    if (g.xcd_map == 2) {
+      grid = nc;  // one chunk per workgroup
+    } else if (g.xcd_map == 1 && grid >= 8) {
+      grid &= ~7ull;  // XCD-contiguous order needs a multiple of 8
+    } else {
+      g.xcd_map = 0;
+    }
+    g.grid = grid ? (uint32_t)grid : 1;  // the head/tail elements still need a workgroup
+    segs.push_back(g);
+    first += nc;
+  } while (first < nchunks);
+}
+
 hipError_t launch_fill(int kind, uint64_t key, uint64_t ctr0, uint64_t n, void* out, const sq_launch_cfg& cfg,
                        hipStream_t s, uint64_t step) {
   const int W = kind_bytes(kind), E = 16 / W;
@@ -840,31 +884,33 @@ hipError_t launch_fill(int kind, uint64_t key, uint64_t ctr0, uint64_t n, void* 
   uint64_t head = mis ? (1024u - mis) / W : 0;
   if (head > n) head = n;
   a.head = (uint32_t)head;
-  a.nvec = (n - head) / E;
-  a.tail = (uint32_t)(n - head - a.nvec * E);
-  const uint64_t per_chunk = (uint64_t)cfg.block * cfg.unroll;
-  a.nchunks = (a.nvec + per_chunk - 1) / per_chunk;
-  a.full_chunks = a.nvec / per_chunk;
+  const uint64_t nvec = (n - head) / E;
+  a.body_nvec = nvec;
+  a.tail = (uint32_t)(n - head - nvec * E);
   const bool split = kind == SQ_U32X2 || kind == SQ_F32X2;  // head is even: out is 8-byte aligned
   a.step = step;
   a.dkey = step * key;
-  a.y_body = (ctr0 + (split ? head / 2 : head) * step) * key;
+  const uint64_t y_body = (ctr0 + (split ? head / 2 : head) * step) * key;
   a.ekey = (uint64_t)(split ? 2 : E) * a.dkey;
-  uint64_t grid = (uint64_t)device_info().cus * cfg.grid_per_cu;
-  if (grid > a.nchunks) grid = a.nchunks;
-  a.xcd_map = cfg.xcd_map;
-  if (a.xcd_map == 2 && a.nchunks < (1ull << 31)) {
-    grid = a.nchunks;  // one chunk per workgroup
-  } else if (a.xcd_map == 1 && grid >= 8) {
-    grid &= ~7ull;     // XCD-contiguous order needs a multiple of 8
-  } else {
-    if (a.xcd_map == 2) grid = std::min<uint64_t>(a.nchunks, (uint64_t)device_info().cus * 64);
-    a.xcd_map = 0;
-  }
-  if (grid == 0) grid = 1;                      // the head/tail elements still need a workgroup
+  unsigned char* body = a.out + head * W;
+  const uint64_t per_chunk = (uint64_t)cfg.block * cfg.unroll;
+  std::vector<FillSegment> segs;
+  plan_fill(nvec, cfg, (uint32_t)device_info().cus, segs);
   const FillKernel k = step == 1 ? fill_kernel<false>(kind, cfg.unroll) : fill_kernel<true>(kind, cfg.unroll);
-  hipLaunchKernelGGL(k, dim3((uint32_t)grid), dim3(cfg.block), 0, s, a);
-  return hipGetLastError();
+  for (size_t i = 0; i < segs.size(); ++i) {
+    const FillSegment& g = segs[i];
+    a.body = body + g.first_chunk * per_chunk * 16;
+    a.y_body = y_body + g.first_chunk * per_chunk * a.ekey;
+    a.nchunks = g.nchunks;
+    a.full = g.full;
+    a.rem = g.rem;
+    a.xcd_map = g.xcd_map;
+    a.edges = i == 0;
+    hipLaunchKernelGGL(k, dim3(g.grid), dim3(cfg.block), 0, s, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_keys(int kind, uint64_t ctr, const uint64_t* keys, uint64_t m, void* out, const sq_launch_cfg& cfg,
