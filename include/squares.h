@@ -193,6 +193,22 @@ int sq_reduce(sq_kind kind, uint64_t key, uint64_t ctr0, uint64_t n, sq_sum_resu
               void *ws, size_t ws_bytes, void *stream);
 int sq_reduce_cfg(sq_kind kind, uint64_t key, uint64_t ctr0, uint64_t n, sq_sum_result *out,
                   void *ws, size_t ws_bytes, const sq_launch_cfg *cfg, void *stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, allocation-free serving loops): sq_reduce with the workspace
+ * taken from a fixed scratch array that the library holds on each device
+ * (1 MiB + 256 bytes, in the library's code object, kept until the process
+ * ends) instead of a `ws` argument.  Nothing on this path allocates.  The
+ * result equals sq_reduce's for the same arguments; `out` is a device
+ * pointer to one sq_sum_result (8-byte aligned), n == 0 writes a zero
+ * result.  The scratch is shared by every call on a device and keeps the
+ * last call's contents: calls that overlap on one device (two streams, two
+ * host threads) race and must be ordered on one stream.  Errors: SQ_EINVAL
+ * (unknown kind, null out), SQ_EALIGN, SQ_ENOMEM (a workspace need beyond the
+ * scratch; sq_reduce_workspace_bytes(n) does not depend on n, so this does
+ * not occur for any n today), SQ_EHIP (including a failed lookup of the
+ * scratch's device address). */
+int sq_reduce_noalloc(sq_kind kind, uint64_t key, uint64_t ctr0, uint64_t n, sq_sum_result *out,
+                      void *stream);
 
 /* Paired sums: the 32-bit and the 64-bit sum over the same counters in one
  * pass.  squares32 at a counter is the high word of squares64 at it (both

@@ -28,6 +28,16 @@ int fail_hip(hipError_t e, const char* what) {
   return SQ_EHIP;
 }
 
+// Scratch of sq_reduce_noalloc: the reduce's workspace as a file-scope
+// device array, so that callers that cannot allocate (code under HIP graph
+// capture, allocation-free serving loops) need no workspace.  Every device
+// the library runs on holds its own copy until the process ends.  In host
+// code `scratch` only names the symbol: its device address, different on
+// each device, comes from hipGetSymbolAddress (ensure_init, once per device)
+// and only that address is passed to kernels.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+static_assert(kNoAllocScratchBytes == 16ull * kReduceMaxParts + 256, "scratch holds the reduce workspace");
+
 static std::mutex g_dev_mu;
 static std::unordered_map<int, DeviceInfo> g_devs;
 static thread_local DeviceInfo t_cur;
@@ -48,6 +58,10 @@ int ensure_init() {
       e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
       if (e != hipSuccess) return fail_hip(e, "hipDeviceGetAttribute(CU count)");
       di.cus = cus > 0 ? cus : 256;
+      // with `dev` current: this device's address of the scratch array
+      void* p = nullptr;
+      di.scratch_err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      di.scratch = di.scratch_err == hipSuccess ? p : nullptr;
       it = g_devs.emplace(dev, di).first;
     }
     t_cur = it->second;
@@ -280,6 +294,25 @@ int sq_reduce(sq_kind kind, uint64_t key, uint64_t ctr0, uint64_t n, sq_sum_resu
   SQ_INIT_OR_RETURN();
   const sq_launch_cfg cfg = tuned_cfg(SQ_OP_REDUCE, kind, n);
   return sq_reduce_cfg(kind, key, ctr0, n, out, ws, ws_bytes, &cfg, stream);
+}
+
+// The reduce on the library's file-scope scratch instead of a workspace
+// argument: no allocation anywhere on this path (sq_reduce_workspace_bytes
+// does not grow with n, so every n fits the fixed scratch).  The queue
+// counter in it is reset by a kernel at the start of each call, and every
+// partial that the final kernel reads is written by the same call.  Calls
+// that overlap on one device share the scratch and race.
+int sq_reduce_noalloc(sq_kind kind, uint64_t key, uint64_t ctr0, uint64_t n, sq_sum_result* out, void* stream) {
+  if (kind_bytes(kind) == 0) return fail(SQ_EINVAL, "unknown kind " + std::to_string((int)kind));
+  SQ_INIT_OR_RETURN();
+  const DeviceInfo& di = device_info();
+  if (di.scratch == nullptr) return fail_hip(di.scratch_err, "hipGetSymbolAddress(scratch) of sq_reduce_noalloc");
+  if (sq_reduce_workspace_bytes(n) > kNoAllocScratchBytes)
+    return fail(SQ_ENOMEM, "reduce workspace of " + std::to_string(sq_reduce_workspace_bytes(n)) +
+                               " bytes exceeds the no-allocation scratch of " + std::to_string(kNoAllocScratchBytes) +
+                               " bytes");
+  const sq_launch_cfg cfg = tuned_cfg(SQ_OP_REDUCE, kind, n);
+  return sq_reduce_cfg(kind, key, ctr0, n, out, di.scratch, kNoAllocScratchBytes, &cfg, stream);
 }
 
 // ---------------------------------------------------------------- paired sums

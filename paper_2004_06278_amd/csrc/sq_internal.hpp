@@ -60,7 +60,12 @@ __host__ __device__ inline double round_scaled(uint64_t lo, uint64_t hi, int e) 
 struct DeviceInfo {
   int device = -1;
   int cus = 256;
+  void* scratch = nullptr;               // this device's copy of the no-allocation reduce scratch
+  hipError_t scratch_err = hipSuccess;   // why scratch is null, if it is
 };
+// Bytes of the file-scope device scratch that sq_reduce_noalloc uses in place
+// of a caller's workspace (the reduce's 128-bit partials and queue counter).
+constexpr size_t kNoAllocScratchBytes = 16ull * 65536 + 256;
 int ensure_init();                 // binds device info for the current device
 const DeviceInfo& device_info();
 

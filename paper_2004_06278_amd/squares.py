@@ -86,6 +86,7 @@ SIGNATURES = {
     "sq_reduce_workspace_bytes": (ctypes.c_size_t, [_u64]),
     "sq_reduce": (_int, [_int, _u64, _u64, _u64, _vp, _vp, ctypes.c_size_t, _vp]),
     "sq_reduce_cfg": (_int, [_int, _u64, _u64, _u64, _vp, _vp, ctypes.c_size_t, ctypes.POINTER(LaunchCfg), _vp]),
+    "sq_reduce_noalloc": (_int, [_int, _u64, _u64, _u64, _vp, _vp]),
     "sq_reduce_pair": (_int, [_int, _u64, _u64, _u64, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "sq_reduce_pair_cfg": (_int, [_int, _u64, _u64, _u64, _vp, _vp, _vp, ctypes.c_size_t,
                                   ctypes.POINTER(LaunchCfg), _vp]),
@@ -331,6 +332,13 @@ def reduce_async(kind: int, key: int, ctr0: int, n: int, result, ws, stream=None
         check(lib().sq_reduce(*args, _stream(stream)))
     else:
         check(lib().sq_reduce_cfg(*args, ctypes.byref(launch_cfg), _stream(stream)))
+
+
+def reduce_noalloc_async(kind: int, key: int, ctr0: int, n: int, result, stream=None) -> None:
+    """The fused exact sum on the library's own device scratch (no workspace
+    argument, no allocation in the call); `result` is a 32-byte CUDA tensor."""
+    _out(result, 32, _torch().uint8)
+    check(lib().sq_reduce_noalloc(kind, key & M64, ctr0 & M64, n, _ptr(result), _stream(stream)))
 
 
 def reduce_strided_async(kind: int, key: int, ctr0: int, step: int, n: int, result, ws, stream=None,
