@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -145,5 +146,12 @@ hipError_t launch_batch(const BatchDesc& d, void* ws, const sq_launch_cfg& cfg, 
 hipError_t launch_batch_body(const BatchDesc& d, const uint32_t* m_dev, void* ws, const sq_launch_cfg& cfg,
                              hipStream_t s);
 
+// The autotuner's acceptance check: `run` writes a candidate's output into
+// `buf` after `buf` was filled with a poison pattern (twice, two patterns);
+// *same is true only if the first `bytes` bytes (a multiple of 4) equal
+// `ref` both times, so a candidate that leaves any word unwritten fails.
+// `bad` is a device counter of 8 bytes.
+hipError_t tune_check_output(const void* ref, void* buf, uint64_t bytes, hipStream_t s, unsigned long long* bad,
+                             const std::function<hipError_t()>& run, bool* same);
 
 }  // namespace sqi

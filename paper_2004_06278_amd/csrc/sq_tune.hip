@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -147,19 +148,33 @@ struct Scratch {
   }
 };
 
-static hipError_t same_bytes(Scratch& S, uint64_t bytes, bool* same) {
-  hipError_t e = hipMemsetAsync(S.bad, 0, sizeof(unsigned long long), S.s);
-  if (e != hipSuccess) return e;
-  const uint64_t words = bytes / 4;
-  hipLaunchKernelGGL(k_count_diff, dim3(device_info().cus * 8), dim3(256), 0, S.s, (const uint32_t*)S.a,
-                     (const uint32_t*)S.b, words, S.bad);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  unsigned long long h = 1;
-  e = hipMemcpyAsync(&h, S.bad, sizeof h, hipMemcpyDeviceToHost, S.s);
-  if (e == hipSuccess) e = hipStreamSynchronize(S.s);
-  *same = (h == 0);
-  return e;
+// Acceptance check of a candidate configuration.  The timed runs alternate
+// the incumbent and the candidate in one buffer, so a candidate that left
+// part of the range unwritten would show the incumbent's bytes there and
+// pass a plain compare.  Here the candidate runs alone into the buffer after
+// it has been filled with a poison pattern, twice, with two patterns that
+// differ in every byte (0xA5..., 0x5A...): a word the candidate does not
+// write keeps the poison in at least one run and differs from the
+// reference.  `bytes` is a multiple of 4.
+hipError_t tune_check_output(const void* ref, void* buf, uint64_t bytes, hipStream_t s, unsigned long long* bad,
+                             const std::function<hipError_t()>& run, bool* same) {
+  *same = false;
+  for (const int poison : {0xA5, 0x5A}) {
+    hipError_t e = hipMemsetAsync(buf, poison, bytes, s);
+    if (e == hipSuccess) e = run();
+    if (e == hipSuccess) e = hipMemsetAsync(bad, 0, sizeof(unsigned long long), s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_count_diff, dim3(device_info().cus * 8), dim3(256), 0, s, (const uint32_t*)ref,
+                       (const uint32_t*)buf, bytes / 4, bad);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    unsigned long long h = 1;
+    e = hipMemcpyAsync(&h, bad, sizeof h, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    if (h != 0) return hipSuccess;
+  }
+  *same = true;
+  return hipSuccess;
 }
 
 // Times the incumbent and a candidate in alternation (reps pairs after one
@@ -365,7 +380,9 @@ int sq_autotune(uint32_t op_mask, uint64_t max_bytes, const char* save_path) {
               [&] { return launch_fill(kind, key, ctr0, n, (unsigned char*)S.b, c, S.s); }, ctx, 5, &ms_inc, &ms);
           if (e != hipSuccess) break;
           bool same = false;
-          if ((e = same_bytes(S, n * W, &same)) != hipSuccess) break;
+          e = tune_check_output(S.a, S.b, n * W, S.s, S.bad,
+                                [&] { return launch_fill(kind, key, ctr0, n, (unsigned char*)S.b, c, S.s); }, &same);
+          if (e != hipSuccess) break;
           report("fill", kind, b, n, c, ms, same);
           if (same && ms < 0.98f * ms_inc) best_c = c;
         }
@@ -400,11 +417,10 @@ int sq_autotune(uint32_t op_mask, uint64_t max_bytes, const char* save_path) {
               S, [&] { return launch_reduce(kind, key, ctr0, n, cand, ws, inc, S.s); },
               [&] { return launch_reduce(kind, key, ctr0, n, cand, ws, c, S.s); }, 5, &ms_inc, &ms);
           if (e != hipSuccess) break;
-          sq_sum_result h[2];
-          if ((e = hipMemcpyAsync(&h[0], res, sizeof h[0], hipMemcpyDeviceToHost, S.s)) != hipSuccess) break;
-          if ((e = hipMemcpyAsync(&h[1], cand, sizeof h[1], hipMemcpyDeviceToHost, S.s)) != hipSuccess) break;
-          if ((e = hipStreamSynchronize(S.s)) != hipSuccess) break;
-          const bool same = std::memcmp(&h[0], &h[1], sizeof h[0]) == 0;
+          bool same = false;
+          e = tune_check_output(res, cand, sizeof(sq_sum_result), S.s, S.bad,
+                                [&] { return launch_reduce(kind, key, ctr0, n, cand, ws, c, S.s); }, &same);
+          if (e != hipSuccess) break;
           report("reduce", kind, b, n, c, ms, same);
           if (same && ms < 0.98f * ms_inc) best_c = c;
         }
@@ -429,10 +445,12 @@ int sq_autotune(uint32_t op_mask, uint64_t max_bytes, const char* save_path) {
       uint64_t rng = 12345 + b, pos = 0;
       while (keys.size() < 4096) {
         const double u = (double)(splitmix(rng) >> 11) * 0x1p-53;
-        const uint64_t len = (uint64_t)std::exp2(lo_e + (hi_e - lo_e) * u);
         const uint8_t kd = (uint8_t)(splitmix(rng) & 3);
         const uint64_t W = kd < 2 ? 4 : 8;
-        pos = (pos + 7) & ~7ull;
+        // 4-byte streams of even length: every offset stays 8-byte aligned,
+        // so the streams cover [0, pos) without gaps and the acceptance
+        // check can compare the whole range
+        const uint64_t len = std::max<uint64_t>((uint64_t)std::exp2(lo_e + (hi_e - lo_e) * u) & ~1ull, 2);
         if (pos + len * W > budget) break;
         keys.push_back(splitmix(rng));
         ctrs.push_back(splitmix(rng));
@@ -489,7 +507,8 @@ int sq_autotune(uint32_t op_mask, uint64_t max_bytes, const char* save_path) {
                       [&] { return launch_batch(d, ws, c, S.s); }, 5, &ms_inc, &ms);
         if (e != hipSuccess) break;
         bool same = false;
-        if ((e = same_bytes(S, used, &same)) != hipSuccess) break;
+        e = tune_check_output(S.a, S.b, pos, S.s, S.bad, [&] { return launch_batch(d, ws, c, S.s); }, &same);
+        if (e != hipSuccess) break;
         report("batch", -1, b, pos, c, ms, same);
         if (same && ms < 0.98f * ms_inc) best_c = c;
       }

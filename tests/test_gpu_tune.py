@@ -72,3 +72,20 @@ def test_autotune_reduce_and_batch_table_valid_and_exact(sq, oracle_mod, tmp_pat
         assert got.tobytes() == ref.tobytes()
     finally:
         assert sq.lib().sq_tune_load(sq.TUNE_TABLE.encode()) == 0
+
+
+def test_acceptance_check_rejects_partial_output():
+    """The tuner accepts a candidate only if a run of it alone, into a
+    poisoned buffer, reproduces the reference: shapes that write every byte
+    pass, runs that skip the first or last output, write half, or write
+    nothing (fills and sums) are rejected (tests/tune_check.hip)."""
+    import os
+    import subprocess
+
+    exe = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_check")
+    assert os.path.exists(exe), "tests/tune_check is not built (run __graft_entry__.build())"
+    log("tune_check program")
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    print(r.stdout)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert r.stdout.strip().endswith("ok")
