@@ -101,6 +101,92 @@ def traffic_from_pmc(fetch_csv: str, write_csv: str, log2n: int) -> dict:
             "kernels": kernels, "detail": detail}
 
 
+def measure_lib():
+    """libsqmeasure.so (paper_2004_06278_amd/calib/sq_measure.hip): the store-only
+    ceiling kernel and the clock sampler.  Built by __graft_entry__.build()."""
+    import ctypes
+
+    from paper_2004_06278_amd import build as b
+
+    if not os.path.exists(b.MEASURE_LIB):
+        raise RuntimeError(f"{b.MEASURE_LIB} is missing: build it first (__graft_entry__.build())")
+    L = ctypes.CDLL(b.MEASURE_LIB)
+    L.sqm_store_ceiling.restype = ctypes.c_int
+    L.sqm_store_ceiling.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p]
+    L.sqm_clock_sampler.restype = ctypes.c_int
+    L.sqm_clock_sampler.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p]
+    return L
+
+
+def run_metadata(torch) -> dict:
+    """Where and on what the line was measured."""
+    import subprocess
+
+    rev = None
+    try:
+        rev = subprocess.run(["git", "-C", ROOT, "rev-parse", "--short=12", "HEAD"], capture_output=True, text=True,
+                             timeout=10).stdout.strip() or None
+    except (OSError, subprocess.SubprocessError):
+        pass
+    prop = torch.cuda.get_device_properties(0)
+    return {"git_rev": rev, "kernel_source_sha": kernel_source_sha(), "device": prop.name,
+            "gfx_arch": getattr(prop, "gcnArchName", None), "cus": prop.multi_processor_count,
+            "hip": getattr(torch.version, "hip", None), "torch": torch.__version__}
+
+
+def clock_from_samples(raw) -> dict:
+    """Mean shader clock over the sampler's window from (clock64, wall_clock64)
+    pairs: the shader clock counter against the 100 MHz real-time counter."""
+    import numpy as np
+
+    s = np.asarray(raw, dtype=np.uint64).reshape(-1, 2).astype(np.float64)
+    dc, dw = np.diff(s[:, 0]), np.diff(s[:, 1])
+    ok = dw > 0
+    per = dc[ok] / dw[ok] * 0.1  # GHz over each interval
+    mean = (s[-1, 0] - s[0, 0]) / max(s[-1, 1] - s[0, 1], 1) * 0.1
+    return {"mean_ghz": round(float(mean), 3), "p10_ghz": round(float(np.percentile(per, 10)), 3),
+            "p90_ghz": round(float(np.percentile(per, 90)), 3), "samples": int(s.shape[0]),
+            "window_ms": round(float((s[-1, 1] - s[0, 1]) * 1e-5), 2),
+            "method": "one wave on a side stream records the shader clock counter (s_memtime) and the 100 MHz "
+                      "real-time counter (s_memrealtime) at a fixed spacing over the timed steps; one XCD"}
+
+
+def valu_from_pmc(csv_path: str, log2n: int) -> dict:
+    """Measured VALU instructions per output and shader clock of the step and
+    uniform-fill kernels, and of the ragged batch's fill kernel, from a
+    rocprofv3 --pmc GRBM_GUI_ACTIVE SQ_INSTS_VALU run of this benchmark
+    (SQ_INSTS_VALU counts wave instructions: x 64 lanes / outputs)."""
+    import csv
+    import re
+
+    from paper_2004_06278_amd import workloads as W
+
+    n = 1 << log2n
+    pats = dict(KERNEL_NAMES)
+    pats.update({"uniform_f32_fill": r"k_fill<1,\d+,false>", "uniform_f64_fill": r"k_fill<3,\d+,false>",
+                 "batch_fill": r"k_batch_fill<\d+>"})
+    outputs = {k: n for k in pats}
+    outputs["batch_fill"] = W.ragged_batch(seed=3).total_outputs
+    disp = {}
+    for r in csv.DictReader(open(csv_path)):
+        d = disp.setdefault(int(r["Dispatch_Id"]), {"name": r["Kernel_Name"].replace(" ", "").replace(
+            "(anonymousnamespace)::", ""), "ns": int(r["End_Timestamp"]) - int(r["Start_Timestamp"])})
+        d[r["Counter_Name"]] = float(r["Counter_Value"])
+    kernels = {}
+    for key, pat in pats.items():
+        rows = [d for d in disp.values() if re.search(pat, d["name"]) and "SQ_INSTS_VALU" in d]
+        # the batch extra also replays small batches; keep dispatches of the full workload's size
+        rows = [d for d in rows if d["SQ_INSTS_VALU"] * 64 / outputs[key] > 5]
+        if not rows:
+            continue
+        valu = sorted(d["SQ_INSTS_VALU"] * 64 / outputs[key] for d in rows)
+        clk = sorted(d.get("GRBM_GUI_ACTIVE", 0) / 8 / d["ns"] for d in rows)
+        kernels[key] = {"valu_instr_per_output": round(valu[len(valu) // 2], 3), "dispatches": len(rows),
+                        "clock_ghz_min_median_max": [round(clk[0], 2), round(clk[len(clk) // 2], 2),
+                                                     round(clk[-1], 2)]}
+    return {"source_sha": kernel_source_sha(), "log2n": log2n, "kernels": kernels}
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -108,14 +194,17 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--log2n", type=int, default=32)
     p.add_argument("--no-extras", action="store_true")
-    p.add_argument("--extras", default="concurrent,uniform,pair,split,modes,batch,serving",
+    p.add_argument("--extras", default="concurrent,uniform,pair,split,modes,batch,batch_wrap,serving",
                    help="comma list of extra measurements after the step "
-                        "(concurrent, uniform, pair, split, modes, batch, serving)")
+                        "(concurrent, uniform, pair, split, modes, batch, batch_wrap, serving)")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--calib-copy", action="store_true",
                    help="run a plain 4 GiB device copy first (scales HBM byte counters)")
     p.add_argument("--traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                    help="write profiles/traffic.json from two rocprofv3 --pmc counter_collection.csv files")
+    p.add_argument("--valu", metavar="PMC_CSV",
+                   help="write profiles/valu.json from a rocprofv3 --pmc GRBM_GUI_ACTIVE SQ_INSTS_VALU "
+                        "counter_collection.csv of this benchmark")
     return p.parse_args()
 
 
@@ -202,6 +291,66 @@ def batch_speedup(sq, torch) -> dict:
             "graph_gnum_s": round(n / t_plan / 1e9, 1), "per_stream_gnum_s": round(n / t_each / 1e9, 1),
             "speedup": round(t_each / t_plan, 2), "graph_gb_s": round(4 * n / t_plan / 1e9, 1),
             "misaligned_graph_ms": round(t_mis * 1e3, 3)}
+
+
+def batch_wrap_speedup(sq, torch) -> dict:
+    """The wrap and width stress: 65536 squares64 streams (U64/F64), lengths
+    uniform in [1, 65536], counters starting within 2^16 of 2^64 (about half
+    pass 2^64 - 1): one replay of the captured batch plan against the 65536
+    per-stream fill launches (best of 5 and of 2, wall clock with a device
+    synchronisation).  Outputs of both are compared with each other and
+    sampled against the oracle outside the timed region."""
+    import numpy as np
+
+    from oracle import oracle
+    from paper_2004_06278_amd import workloads as W
+
+    b = W.wrap_batch(seed=4)
+    db = sq.batch_to_device(b.keys, b.ctr0s, b.lens, b.offs, b.kinds, b.arena_bytes)
+    plan = sq.BatchPlan(db)
+
+    def per_stream():
+        sq.fill_streams(b.keys, b.ctr0s, b.lens, b.offs, b.kinds, db.out, b.arena_bytes)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        best = 1e30
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        return best
+
+    t_plan = timed(plan.launch, 5)
+    a = db.out[: b.arena_bytes].clone()
+    t_each = timed(per_stream, 2)
+    same = bool(torch.equal(a, db.out[: b.arena_bytes]))
+    del a
+    # a few streams against the oracle (the parity tests compare every output)
+    g = np.random.Generator(np.random.PCG64(44))
+    host = db.out[: b.arena_bytes]
+    bad = 0
+    for s in g.integers(0, b.m, size=16):
+        s = int(s)
+        k, W8 = int(b.kinds[s]), 8
+        off, ln = int(b.offs[s]), int(b.lens[s])
+        got = host[off: off + W8 * ln].cpu().numpy().tobytes()
+        ref = oracle.fill(k, int(b.keys[s]), int(b.ctr0s[s]), ln).view(np.uint8).tobytes()
+        bad += got != ref
+    plan.close()
+    n = b.total_outputs
+    del db, host
+    torch.cuda.empty_cache()
+    gbs = 8 * n / t_plan / 1e9
+    return {"workload": "65536 squares64 streams, lengths uniform 1..65536, ctr0 within 2^16 of 2^64 (wrapping), "
+                        "U64/F64", "outputs": n, "bytes": 8 * n,
+            "graph_ms": round(t_plan * 1e3, 3), "per_stream_ms": round(t_each * 1e3, 3),
+            "graph_gnum_s": round(n / t_plan / 1e9, 1), "per_stream_gnum_s": round(n / t_each / 1e9, 1),
+            "speedup": round(t_each / t_plan, 2), "graph_gb_s": round(gbs, 1),
+            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "graph_equals_per_stream": same,
+            "oracle_sampled_streams": 16, "oracle_mismatches": int(bad)}
 
 
 def paired_sums(sq, torch, key: int, ctr0: int, n: int, steady_ms: dict) -> dict:
@@ -330,9 +479,10 @@ def concurrent_step(sq, torch, key: int, ctr0: int, n: int, serial_ms: float, st
             "vs_serial_step": round(serial_ms / ms, 3), "streams": 2}
 
 
-def uniform_fills(sq, torch, key: int, ctr0: int, n: int) -> dict:
+def uniform_fills(sq, torch, key: int, ctr0: int, n: int, valu: dict | None = None) -> dict:
     """The uniform fills over the same n counters: F32 (16 GiB) and F64
-    (32 GiB), conversion fused into the generating kernel."""
+    (32 GiB), conversion fused into the generating kernel, back to back
+    (mean of 10 after 2)."""
     r = {}
     for name, kind, W in (("uniform_f32", sq.F32, 4), ("uniform_f64", sq.F64, 8)):
         out = torch.empty(n * W, dtype=torch.uint8, device="cuda")
@@ -340,6 +490,8 @@ def uniform_fills(sq, torch, key: int, ctr0: int, n: int) -> dict:
         gbs = W * n / (ms * 1e-3) / 1e9
         r[name] = {"n": n, "ms": round(ms, 4), "gnum_s": round(n / (ms * 1e-3) / 1e9, 1), "gb_s": round(gbs, 1),
                    "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+        if valu and name + "_fill" in valu:
+            r[name]["valu_instr_per_output_measured"] = valu[name + "_fill"]["valu_instr_per_output"]
         del out
         torch.cuda.empty_cache()
     return r
@@ -383,6 +535,12 @@ def counter_modes(sq, torch, key: int, ctr0: int, n: int, per_op_ms: dict) -> di
 
 def main() -> int:
     args = parse()
+    if args.valu:
+        t = valu_from_pmc(args.valu, args.log2n)
+        with open(os.path.join(ROOT, "profiles", "valu.json"), "w") as f:
+            json.dump(t, f, indent=1)
+        print(json.dumps(t))
+        return 0
     if args.traffic:
         t = traffic_from_pmc(args.traffic[0], args.traffic[1], args.log2n)
         with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
@@ -435,14 +593,31 @@ def main() -> int:
             else:
                 fn()
 
+    mlib = measure_lib()
+    est_ms = 1e30
     for _ in range(args.warmup):
+        tw = time.perf_counter()
         step(False)
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        est_ms = min(est_ms, (time.perf_counter() - tw) * 1e3)
+    # The clock sampler runs on a side stream over the first ~70% of the timed
+    # region (its length is fixed when it is launched, so it must end before
+    # the timed steps do: the final device synchronisation waits for it).
+    nsamp = 2048
+    samples = torch.zeros(2 * nsamp, dtype=torch.int64, device="cuda")
+    side = torch.cuda.Stream()
+    window_ms = 0.7 * est_ms * args.steps
+    sample_clock = args.warmup > 0 and window_ms < 10_000  # no estimate without warm-up steps
+    if sample_clock:
+        spacing = max(int(window_ms * 1e5 / nsamp), 100)  # 100 MHz ticks
+        rc = mlib.sqm_clock_sampler(samples.data_ptr(), nsamp, spacing, side.cuda_stream)
+        assert rc == 0, f"clock sampler launch failed ({rc})"
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step(True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    clock = clock_from_samples(samples.cpu().numpy()) if sample_clock else None
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     per_op_ms = {name: sum(a.elapsed_time(b) for a, b in ev[name]) / len(ev[name]) for name in ev}
     per_op_sorted = {name: sorted(a.elapsed_time(b) for a, b in ev[name]) for name in ev}
@@ -462,26 +637,51 @@ def main() -> int:
     s64, v64, _ = sq.read_result(res64)
     assert abs(v32 / n - 0.5) < 1e-3 and abs(v64 / n - 0.5) < 1e-3
 
-    # measured store ceiling at the same size: torch's plain fill kernel over
-    # the 16 GiB output buffer (outside the timed region)
-    store_ms = _event_ms(torch, lambda: out32.fill_(1), reps=5)
-    store_gbs = 4 * n / (store_ms * 1e-3) / 1e9
+    # Store-only ceiling in exactly the squares64 fill's launch shape and size
+    # (one 4 KiB chunk per workgroup, 256 lanes x one 16-byte store, 2^n x 8
+    # bytes of constant data), back to back, outside the timed region.
+    store_ms = _event_ms(torch, lambda: mlib.sqm_store_ceiling(out64.data_ptr(), 8 * n, 7,
+                                                               torch.cuda.current_stream().cuda_stream),
+                         reps=10, warm=3)
+    store_gbs = 8 * n / (store_ms * 1e-3) / 1e9
+    store_ceiling = {"ms": round(store_ms, 4), "gb_s": round(store_gbs, 1), "hbm_frac": round(store_gbs / HBM_PEAK_GBS, 4),
+                     "kernel": "k_store_chunk (paper_2004_06278_amd/calib/sq_measure.hip)",
+                     "shape": f"one 4 KiB chunk per workgroup, 256 lanes x one 16-byte global_store_dwordx4, "
+                              f"2^{args.log2n} x 8 B, constant data, back to back"}
+    valu_file = os.path.join(ROOT, "profiles", "valu.json")
+    valu = {}
+    if os.path.exists(valu_file):
+        with open(valu_file) as f:
+            vt = json.load(f)
+        # counts taken on other kernel sources or another size do not apply
+        if vt.get("source_sha") == kernel_source_sha() and vt.get("log2n") == args.log2n:
+            valu = vt.get("kernels", {})
 
     def hbm_roof(name, nbytes, ms_by_op=per_op_ms):
         ms = ms_by_op[name]
         gbs = nbytes / (ms * 1e-3) / 1e9
-        return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": name, "avg_ms": round(ms, 4), "algorithmic_bytes": nbytes,
-                "measured_store_ceiling_gbs": round(store_gbs, 1),
-                "frac_of_store_ceiling": round(gbs / store_gbs, 4)}
+        r = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+             "kernel": name, "avg_ms": round(ms, 4), "algorithmic_bytes": nbytes,
+             "measured_store_ceiling_gbs": round(store_gbs, 1)}
+        if name in valu:
+            r["valu_instr_per_output_measured"] = valu[name]["valu_instr_per_output"]
+        return r
 
     def alu_roof(name, slots, ms_by_op=per_op_ms):
         ms = ms_by_op[name]
         rate = slots * n / (ms * 1e-3)
-        return {"bound": "alu", "achieved": round(rate / 1e12, 3), "peak": round(ALU_PEAK_SLOTS / 1e12, 3),
-                "unit": "T VALU-slot/s", "frac": round(rate / ALU_PEAK_SLOTS, 4), "traffic": None,
-                "kernel": name, "avg_ms": round(ms, 4), "slots_per_output": slots}
+        r = {"bound": "alu", "achieved": round(rate / 1e12, 3), "peak": round(ALU_PEAK_SLOTS / 1e12, 3),
+             "unit": "T VALU-slot/s", "frac": round(rate / ALU_PEAK_SLOTS, 4), "traffic": None,
+             "kernel": name, "avg_ms": round(ms, 4), "slots_per_output": slots}
+        if name in valu:
+            # the same roofline from the executed instruction count (rocprofv3
+            # SQ_INSTS_VALU), every VALU instruction counted as one issue slot
+            v = valu[name]["valu_instr_per_output"]
+            irate = v * n / (ms * 1e-3)
+            r["measured"] = {"valu_instr_per_output": v, "achieved": round(irate / 1e12, 3),
+                             "unit": "T VALU-instr/s", "frac": round(irate / ALU_PEAK_SLOTS, 4)}
+        return r
 
     rooflines = {
         "sq32_fill": hbm_roof("sq32_fill", 4 * n),
@@ -534,6 +734,9 @@ def main() -> int:
         "roofline": rooflines[dominant],
         "rooflines": rooflines,
         "rooflines_steady": rooflines_steady,
+        "store_ceiling": store_ceiling,
+        "clock_in_step": clock,
+        "run": run_metadata(torch),
     }
     del out32, out64
     torch.cuda.empty_cache()
@@ -541,7 +744,7 @@ def main() -> int:
     if "concurrent" in extras:
         line["concurrent_step"] = concurrent_step(sq, torch, key, ctr0, n, ms_per_step)
     if "uniform" in extras:
-        line["uniform_fills"] = uniform_fills(sq, torch, key, ctr0, n)
+        line["uniform_fills"] = uniform_fills(sq, torch, key, ctr0, n, valu)
     if "pair" in extras:
         line["paired_sums"] = paired_sums(sq, torch, key, ctr0, n, steady_ms)
     if "split" in extras:
@@ -550,6 +753,10 @@ def main() -> int:
         line["counter_modes"] = counter_modes(sq, torch, key, ctr0, n, per_op_ms)
     if "batch" in extras:
         line["batch"] = batch_speedup(sq, torch)
+        if "batch_fill" in valu:
+            line["batch"]["valu_instr_per_output_measured"] = valu["batch_fill"]["valu_instr_per_output"]
+    if "batch_wrap" in extras:
+        line["batch_wrap"] = batch_wrap_speedup(sq, torch)
     if "serving" in extras:
         from paper_2004_06278_amd import serve_bench
 

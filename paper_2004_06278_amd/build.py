@@ -64,6 +64,27 @@ def build_calib(verbose: bool = False) -> str:
     return exe
 
 
+MEASURE_LIB = os.path.join(HERE, "calib", "libsqmeasure.so")
+
+
+def build_measure(verbose: bool = False) -> str:
+    """Builds libsqmeasure.so: the benchmark's store-only ceiling kernel and
+    clock sampler (measurement code, not part of libsquares.so)."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    src = os.path.join(HERE, "calib", "sq_measure.hip")
+    tmp = MEASURE_LIB + ".tmp"
+    cmd = [hipcc, *FLAGS, "-shared", src, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("hipcc failed on sq_measure.hip")
+    os.replace(tmp, MEASURE_LIB)
+    return MEASURE_LIB
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
     print(build_calib(verbose=True))
+    print(build_measure(verbose=True))

@@ -845,12 +845,15 @@ void plan_fill(uint64_t nvec, const sq_launch_cfg& cfg, uint32_t cus, std::vecto
   segs.clear();
   const uint64_t per_chunk = (uint64_t)cfg.block * cfg.unroll;
   const uint64_t nchunks = nvec / per_chunk + (nvec % per_chunk != 0);
+  // as few launches as the limit allows, with equal shares of the chunks
   const uint64_t maxc = max_segment_chunks(cfg.block);
+  const uint64_t nseg = nchunks / maxc + (nchunks % maxc != 0);
+  const uint64_t share = nseg > 1 ? nchunks / nseg + (nchunks % nseg != 0) : nchunks;
   uint64_t first = 0;
   do {
     FillSegment g{};
     g.first_chunk = first;
-    const uint64_t nc = std::min<uint64_t>(nchunks - first, maxc);
+    const uint64_t nc = std::min<uint64_t>(nchunks - first, share);
     const uint64_t vecs = std::min<uint64_t>(nvec - first * per_chunk, nc * per_chunk);
     g.nchunks = (uint32_t)nc;
     g.full = (uint32_t)(vecs / per_chunk);

@@ -289,3 +289,18 @@ def test_tune_table_roundtrip(tmp_path):
     # restore the shipped table for later tests in this process
     if os.path.exists(squares.TUNE_TABLE):
         assert L.sq_tune_load(squares.TUNE_TABLE.encode()) == 0
+
+
+def test_fill_launch_plan_on_cpu():
+    """The fill's launch plan (tests/plan_check.cpp, host code of the
+    library): fills of 2^33 8-byte and 2^34 4-byte outputs in the default
+    shape are split into launches below 2^32 work-items that cover every
+    chunk once, in order; other shapes and edge sizes too."""
+    import subprocess
+
+    exe = os.path.join(ROOT, "tests", "plan_check")
+    if not os.path.exists(exe):
+        pytest.fail("tests/plan_check is not built (run __graft_entry__.build())")
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert r.stdout.strip().endswith("ok")

@@ -168,31 +168,6 @@ def test_plain_fill_64mib(sq, oracle_mod):
     assert np.array_equal(x2[1::2], u32)
 
 
-@pytest.mark.parametrize("kind", KINDS)
-def test_full_size_sampled(sq, oracle_mod, kind):
-    """n = 2^32 outputs from a random 64-bit counter under a distinct-digit key,
-    in the launch configuration the benchmark uses: the first and last 2^16
-    outputs and 2^16 random positions equal the oracle's."""
-    import torch
-
-    from paper_2004_06278_amd import workloads as W
-
-    c = W.single_key_case()
-    n = 1 << 32
-    log(f"full-size fill kind={kind} key={c.key:#x} ctr0={c.ctr0:#x} n={n}")
-    out = sq.fill(kind, c.key, c.ctr0, n)
-    W_ = KIND_BYTES[kind]
-    iv = out.view(torch.int32 if W_ == 4 else torch.int64)
-    g = np.random.Generator(np.random.PCG64(55 + kind))
-    idx = np.unique(np.concatenate([np.arange(1 << 16), n - 1 - np.arange(1 << 16),
-                                    g.integers(0, n, size=1 << 16)]))
-    got = iv[torch.from_numpy(idx.astype(np.int64)).cuda()].cpu().numpy().view(np.uint8).reshape(-1, W_)
-    for row, i in zip(got, idx):
-        assert row.tobytes() == oracle_element(oracle_mod, kind, c.key, c.ctr0, int(i)), f"position {int(i)}"
-    del out, iv
-    torch.cuda.empty_cache()
-
-
 @pytest.mark.parametrize("kind", [0, 4])
 def test_fill_past_2p32_outputs(sq, oracle_mod, kind):
     """n = 2^32 + 2^17 + 3 outputs (16 GiB): output indices past 32 bits and
@@ -224,12 +199,13 @@ def test_fill_past_2p32_outputs(sq, oracle_mod, kind):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("kind", [0, 1, 2, 3])
+@pytest.mark.parametrize("kind", KINDS)
 def test_full_size_complete(sq, oracle_mod, kind):
-    """Every one of the n = 2^32 outputs of the single-key workload (U32 and
-    F32: 16 GiB, U64 and F64: 32 GiB), in the benchmark's launch
-    configuration, equals the oracle's: compared in chunks of 2^28 outputs,
-    the oracle running on all host threads into a reused buffer."""
+    """Every one of the n = 2^32 outputs of the single-key workload (U32, F32
+    and the split-word U32X2, F32X2: 16 GiB; U64 and F64: 32 GiB), in the
+    benchmark's launch configuration, equals the oracle's: compared in chunks
+    of 2^28 outputs, the oracle running on all host threads into a reused
+    buffer (a split kind's chunk starts at counter ctr0 + base / 2)."""
     import torch
 
     from paper_2004_06278_amd import workloads as W
@@ -239,17 +215,45 @@ def test_full_size_complete(sq, oracle_mod, kind):
     log(f"full-size complete compare kind={kind} key={c.key:#x} ctr0={c.ctr0:#x} n={n}")
     out = sq.fill(kind, c.key, c.ctr0, n)
     tdt = torch.int32 if KIND_BYTES[kind] == 4 else torch.int64
-    ndt = {0: np.uint32, 1: np.float32, 2: np.uint64, 3: np.float64}[kind]
+    ndt = {0: np.uint32, 1: np.float32, 2: np.uint64, 3: np.float64, 4: np.uint32, 5: np.float32}[kind]
+    per_ctr = 2 if kind in (4, 5) else 1
     flat = out.view(tdt)
     host = torch.empty(chunk, dtype=tdt, pin_memory=True)
     ref = np.empty(chunk, dtype=ndt)
     for base in range(0, n, chunk):
         host.copy_(flat[base: base + chunk])
-        oracle_mod.fill_into(kind, c.key, (c.ctr0 + base) % 2**64, ref, threads=HOST_THREADS)
+        oracle_mod.fill_into(kind, c.key, (c.ctr0 + base // per_ctr) % 2**64, ref, threads=HOST_THREADS)
         got = host.numpy()                      # compared as integers: bit equality, floats included
         want = ref.view(got.dtype)
         if not np.array_equal(got, want):
             bad = int(np.nonzero(got != want)[0][0])
             pytest.fail(f"first mismatch at output {base + bad}")
     del out, flat
+    torch.cuda.empty_cache()
+
+
+def test_fill_2p33_u64_in_two_launches(sq, oracle_mod):
+    """n = 2^33 U64 outputs (64 GiB) in the default shape (one 4 KiB chunk per
+    256-lane workgroup) needs 2^24 workgroups, more than one launch of fewer
+    than 2^32 work-items can hold, so the fill is split into two launches of
+    2^23 chunks.  The 2^15 outputs around the boundary (output 2^32), the
+    first and last 2^14 and 2^12 random positions equal the oracle's."""
+    import torch
+
+    from paper_2004_06278_amd import workloads as W
+
+    c = W.single_key_case(seed=21)
+    n, k = 1 << 33, 1 << 14
+    log(f"fill U64 n=2^33 key={c.key:#x} ctr0={c.ctr0:#x}")
+    out = sq.fill(2, c.key, c.ctr0, n)
+    for a in (0, (1 << 32) - k, n - k):
+        got = out[a: a + (2 * k if a == (1 << 32) - k else k)].cpu().numpy()
+        ref = oracle_mod.fill(2, c.key, (c.ctr0 + a) % 2**64, got.size, threads=HOST_THREADS)
+        assert np.array_equal(got, ref), f"block at {a}"
+    g = np.random.Generator(np.random.PCG64(2033))
+    idx = g.integers(0, n, size=1 << 12)
+    got = out.view(torch.int64)[torch.from_numpy(idx.astype(np.int64)).cuda()].cpu().numpy().view(np.uint8)
+    for row, i in zip(got.reshape(-1, 8), idx):
+        assert row.tobytes() == oracle_element(oracle_mod, 2, c.key, c.ctr0, int(i)), f"position {int(i)}"
+    del out
     torch.cuda.empty_cache()

@@ -8,7 +8,7 @@ import time
 import numpy as np
 import pytest
 
-from gpu_helpers import KIND_BYTES, first_diff, log, oracle_element, to_host_bytes
+from gpu_helpers import HOST_THREADS, KIND_BYTES, first_diff, log, oracle_element, to_host_bytes
 
 pytestmark = pytest.mark.gpu
 
@@ -200,8 +200,9 @@ def test_server_full_size_requests_sampled(sq, oracle_mod):
     configuration (32 GiB budget, 4096 slots, chunks of 2^24 outputs, 4
     lanes): 60 requests of the serving trace (log-uniform 2^10..2^28 outputs,
     70% 32-bit) plus two of 2^28 outputs (U32 and U64, the second wrapping its
-    counter), submitted at once.  Requests below 2^20 outputs are compared
-    whole; larger ones on their first and last 2^14 outputs and 512 random
+    counter), submitted at once.  Requests below 2^20 outputs and the 2^28
+    U32 request are compared whole (the latter in 2^26-output pieces); the
+    other large ones on their first and last 2^14 outputs and 512 random
     positions, each against the oracle."""
     import torch
 
@@ -223,6 +224,13 @@ def test_server_full_size_requests_sampled(sq, oracle_mod):
                 got = to_host_bytes(out)
                 exp = _oracle(oracle_mod, kind, key, ctr0, n)
                 assert got.tobytes() == exp.tobytes(), (q, first_diff(got, exp))
+            elif n == 1 << 28 and kind == 0:
+                # the largest request size, compared whole in 2^26-output pieces
+                piece = 1 << 26
+                for base in range(0, n, piece):
+                    got = to_host_bytes(out[base * W_:(base + piece) * W_])
+                    exp = oracle_mod.fill(kind, key, (ctr0 + base) % 2**64, piece, threads=HOST_THREADS).view(np.uint8)
+                    assert got.tobytes() == exp.tobytes(), (q, base, first_diff(got, exp))
             else:
                 k = 1 << 14
                 head = to_host_bytes(out[: k * W_])
