@@ -41,13 +41,16 @@ CUS, CLOCK_HZ = 256, 2.4e9      # MI355X compute units and peak engine clock
 # (add, shift, xor) issue up to twice as fast and count half a slot.
 # Peak = 256 CUs * 2.4 GHz * 64 lanes (matching fp64 vector 78.6 TFLOP/s).
 ALU_PEAK_SLOTS = CUS * CLOCK_HZ * 64
-# Algorithmic VALU work per output in slots: a round is one 32x32->64
-# multiply-add (1) + one 32-bit multiply (1) + one shift-add (1); the Weyl
-# step to the next counter is one 64-bit add (1).
+# Algorithmic VALU work per output in slots, as the fused sums compute it: a
+# round is one 32x32->64 multiply-add (1) + one 32-bit multiply (1) + one
+# shift-add (1); round 1 of every counter after a run's first comes from
+# running differences (r1 += d, d += 2*key*key: two 64-bit adds, 2 slots
+# instead of the squaring's 3); the Weyl step to the next counter is one
+# 64-bit add (1).
 SLOTS = {
-    "sq32": 4 * 3.0 + 1.0,                 # 13
-    "sq64": 5 * 3.0 + 0.5 + 1.0,           # 16.5 (+ the xor of round 5)
-    "sum_f32": 0.5 + 1.0,                  # >> 8, 64-bit accumulate
+    "sq32": 3 * 3.0 + 2.0 + 1.0,           # 12
+    "sq64": 4 * 3.0 + 2.0 + 0.5 + 1.0,     # 15.5 (+ the xor of round 5)
+    "sum_f32": 0.5 + 1.0,                  # >> 8, 32-bit accumulate (half a 3-input add) + flush share
     "sum_f64": 1.0 + 1.0,                  # 64-bit >> 11, 64-bit accumulate
     "pair_f32": 0.5 + 0.5,                 # the paired sum's F32 term: >> 40, 32-bit accumulate
 }
@@ -249,9 +252,26 @@ def cpu_baseline(key: int, ctr0: int, log2_sample: int = 31) -> dict:
             "host_cpus_visible": os.cpu_count()}
 
 
+def timed_wall(torch, fn, reps: int, warm: int = 2) -> float:
+    """Wall-clock seconds per call of fn over `reps` calls issued back to back
+    (after `warm` untimed calls), with a device synchronisation on both sides:
+    host launch costs count, and the device runs the calls as a caller that
+    issues them in a loop would."""
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
 def batch_speedup(sq, torch) -> dict:
-    """4096 keys, log-uniform lengths in [2^10, 2^24], U32/F32: one replay of the
-    captured batch plan vs 4096 separate fill launches on one stream."""
+    """4096 keys, log-uniform lengths in [2^10, 2^24], U32/F32: replays of the
+    captured batch plan (scan, map and fill kernels) against the same batch as
+    4096 separate fill launches on one stream, each timed per call over calls
+    issued back to back (timed_wall)."""
     from paper_2004_06278_amd import workloads as W
 
     b = W.ragged_batch(seed=3)
@@ -262,18 +282,10 @@ def batch_speedup(sq, torch) -> dict:
         sq.fill_streams(b.keys, b.ctr0s, b.lens, b.offs, b.kinds, db.out, b.arena_bytes)
 
     def timed(fn, reps):
-        fn()
-        torch.cuda.synchronize()
-        best = 1e30
-        for _ in range(reps):
-            t0 = time.perf_counter()
-            fn()
-            torch.cuda.synchronize()
-            best = min(best, time.perf_counter() - t0)
-        return best
+        return timed_wall(torch, fn, reps)
 
-    t_plan = timed(plan.launch, 5)
-    t_each = timed(per_stream, 3)
+    t_plan = timed(plan.launch, 10)
+    t_each = timed(per_stream, 4)
     plan.close()
     n = b.total_outputs
     del db
@@ -282,7 +294,7 @@ def batch_speedup(sq, torch) -> dict:
     bm = W.ragged_batch(seed=3, misalign=True)
     dbm = sq.batch_to_device(bm.keys, bm.ctr0s, bm.lens, bm.offs, bm.kinds, bm.arena_bytes)
     planm = sq.BatchPlan(dbm)
-    t_mis = timed(planm.launch, 5)
+    t_mis = timed(planm.launch, 10)
     planm.close()
     del dbm
     torch.cuda.empty_cache()
@@ -296,9 +308,8 @@ def batch_speedup(sq, torch) -> dict:
 def batch_wrap_speedup(sq, torch) -> dict:
     """The wrap and width stress: 65536 squares64 streams (U64/F64), lengths
     uniform in [1, 65536], counters starting within 2^16 of 2^64 (about half
-    pass 2^64 - 1): one replay of the captured batch plan against the 65536
-    per-stream fill launches (best of 5 and of 2, wall clock with a device
-    synchronisation).  Outputs of both are compared with each other and
+    pass 2^64 - 1): replays of the captured batch plan against the 65536
+    per-stream fill launches (timed_wall, 10 and 2 calls).  Outputs of both are compared with each other and
     sampled against the oracle outside the timed region."""
     import numpy as np
 
@@ -312,20 +323,9 @@ def batch_wrap_speedup(sq, torch) -> dict:
     def per_stream():
         sq.fill_streams(b.keys, b.ctr0s, b.lens, b.offs, b.kinds, db.out, b.arena_bytes)
 
-    def timed(fn, reps):
-        fn()
-        torch.cuda.synchronize()
-        best = 1e30
-        for _ in range(reps):
-            t0 = time.perf_counter()
-            fn()
-            torch.cuda.synchronize()
-            best = min(best, time.perf_counter() - t0)
-        return best
-
-    t_plan = timed(plan.launch, 5)
+    t_plan = timed_wall(torch, plan.launch, 10)
     a = db.out[: b.arena_bytes].clone()
-    t_each = timed(per_stream, 2)
+    t_each = timed_wall(torch, per_stream, 2, warm=1)
     same = bool(torch.equal(a, db.out[: b.arena_bytes]))
     del a
     # a few streams against the oracle (the parity tests compare every output)

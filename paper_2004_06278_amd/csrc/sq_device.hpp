@@ -108,18 +108,34 @@ __device__ __forceinline__ uint32_t round_hi(uint64_t x, uint64_t a) {
   return cross_add(xl, xh, (uint32_t)(m >> 32));
 }
 
-// squares32 from its Weyl terms y = ctr*key, z = (ctr+1)*key.
-__device__ __forceinline__ uint32_t sq32(uint64_t y, uint64_t z) {
-  uint64_t x = round_rot(y, y);  // round 1 (x starts as y)
+// x*x + a (mod 2^64), not rotated.  Round 1 of both generators is
+// rot32(y*y + y): its value before the rotation, r1 = y*y + y, is what the
+// functions below take when a caller supplies it from a running difference
+// (see fd_step) instead of squaring.
+__device__ __forceinline__ uint64_t square_plus(uint64_t x, uint64_t a) {
+  uint32_t lo, hi;
+  round_norot(x, a, lo, hi);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t rot32(uint64_t v) { return (v << 32) | (v >> 32); }  // a register swap
+
+// squares32 from round 1's value r1 = y*y + y and the Weyl terms y = ctr*key,
+// z = (ctr+1)*key.
+__device__ __forceinline__ uint32_t sq32_after1(uint64_t r1, uint64_t y, uint64_t z) {
+  uint64_t x = rot32(r1);        // round 1's rotation
   x = round_rot(x, z);           // round 2
   x = round_rot(x, y);           // round 3
   return round_hi(x, z);         // round 4: upper half of x*x + z
 }
 
-// squares64: round 4 keeps t = x*x + z whole; round 5 squares rot32(t), adds
-// y and its upper 32 bits are XORed into the low word of t.
-__device__ __forceinline__ uint64_t sq64(uint64_t y, uint64_t z) {
-  uint64_t x = round_rot(y, y);
+__device__ __forceinline__ uint32_t sq32(uint64_t y, uint64_t z) { return sq32_after1(square_plus(y, y), y, z); }
+
+// squares64 from round 1's value: round 4 keeps t = x*x + z whole; round 5
+// squares rot32(t), adds y and its upper 32 bits are XORed into the low word
+// of t.
+__device__ __forceinline__ uint64_t sq64_after1(uint64_t r1, uint64_t y, uint64_t z) {
+  uint64_t x = rot32(r1);
   x = round_rot(x, z);
   x = round_rot(x, y);
   uint32_t tl, th;
@@ -128,6 +144,30 @@ __device__ __forceinline__ uint64_t sq64(uint64_t y, uint64_t z) {
   const uint32_t r5 = round_hi(xr, y);
   return ((uint64_t)th << 32) | (tl ^ r5);
 }
+
+__device__ __forceinline__ uint64_t sq64(uint64_t y, uint64_t z) { return sq64_after1(square_plus(y, y), y, z); }
+
+// Round 1 by running differences.  Along Weyl terms y, y+s, y+2s, ...
+// (s = key for consecutive counters, s = step*key for counters `step` apart,
+// s = J*key for counters J apart) round 1's value r1(y) = y*y + y is a
+// quadratic in the position, so modulo 2^64
+//     r1(y + s) = r1(y) + d(y),   d(y) = 2*s*y + s*s + s,
+//     d(y + s)  = d(y) + 2*s*s,
+// two 64-bit adds per counter instead of one squaring (three instructions).
+// The state is (r1, d) at the current y; s2 = 2*s, c = s*s + s and
+// dd = 2*s*s are the step's uniform constants.
+struct FdConst {
+  uint64_t s2, c, dd;
+};
+__device__ __forceinline__ FdConst fd_const(uint64_t s) {
+  FdConst k;
+  k.s2 = 2 * s;
+  k.c = s * s + s;
+  k.dd = 2 * s * s;
+  return k;
+}
+// d at y: 2*s*y + s*s + s
+__device__ __forceinline__ uint64_t fd_diff(uint64_t y, const FdConst& k) { return y * k.s2 + k.c; }
 
 // Exact conversions to [0,1): top 24 bits of a squares32 output, top 53 bits
 // of a squares64 output, each scaled by a power of two.
@@ -257,22 +297,28 @@ __device__ __forceinline__ void store_elem(unsigned char* p, uint64_t ctr0, uint
 }
 
 // The integer a reduce of kind K sums for one counter (the value is that
-// integer times 2^-24 for F32 and F32X2 and 2^-53 for F64).  Split kinds
-// sum both halves of the counter's squares64 output.
+// integer times 2^-24 for F32 and F32X2 and 2^-53 for F64), from round 1's
+// value r1 and the Weyl terms.  Split kinds sum both halves of the
+// counter's squares64 output.
 template <int K>
-__device__ __forceinline__ uint64_t sum_term(uint64_t y, uint64_t z) {
-  if constexpr (K == 0) return sq32(y, z);
-  if constexpr (K == 1) return sq32(y, z) >> 8;
-  if constexpr (K == 2) return sq64(y, z);
-  if constexpr (K == 3) return sq64(y, z) >> 11;
+__device__ __forceinline__ uint64_t sum_term_after1(uint64_t r1, uint64_t y, uint64_t z) {
+  if constexpr (K == 0) return sq32_after1(r1, y, z);
+  if constexpr (K == 1) return sq32_after1(r1, y, z) >> 8;
+  if constexpr (K == 2) return sq64_after1(r1, y, z);
+  if constexpr (K == 3) return sq64_after1(r1, y, z) >> 11;
   if constexpr (K == 4) {
-    const uint64_t v = sq64(y, z);
+    const uint64_t v = sq64_after1(r1, y, z);
     return (v & 0xFFFFFFFFull) + (v >> 32);
   }
   if constexpr (K == 5) {
-    const uint64_t v = sq64(y, z);
+    const uint64_t v = sq64_after1(r1, y, z);
     return (((uint32_t)v) >> 8) + (v >> 40);
   }
+}
+
+template <int K>
+__device__ __forceinline__ uint64_t sum_term(uint64_t y, uint64_t z) {
+  return sum_term_after1<K>(square_plus(y, y), y, z);
 }
 
 // The low-half term of a split kind (the last element of an odd count).

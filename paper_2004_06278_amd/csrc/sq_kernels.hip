@@ -208,12 +208,17 @@ __device__ __forceinline__ void block_sum128(uint64_t& lo, uint64_t& hi) {
 
 // Each thread sums its own contiguous run of counters.  The integer terms
 // are accumulated exactly: in 64 bits over runs short enough not to
-// overflow (FLUSH terms), then into a 128-bit total.
+// overflow (FLUSH terms), then into a 128-bit total.  Round 1 of every
+// counter after the run's first comes from running differences along the
+// run's Weyl terms (two 64-bit adds instead of a squaring; fd_const).
 // Adds the integer terms of cnt consecutive counters, the first with Weyl
 // term y, to the 128-bit (lo, hi).
 template <int K, int U, bool S>
 __device__ __forceinline__ void run_sum(uint64_t y, uint64_t cnt, uint64_t key, uint64_t dkey, uint64_t& lo,
                                         uint64_t& hi) {
+  // Weyl step from one counter of the run to the next, and its differences
+  const FdConst k = fd_const(opaque_uniform(S ? dkey : key));
+  uint64_t r1 = square_plus(y, y), d = fd_diff(y, k);
   if constexpr (K == 2) {
     // 64-bit terms: a 64-bit partial plus a 32-bit count of its carries,
     // folded into the 128-bit total every 2^20 terms
@@ -231,16 +236,20 @@ __device__ __forceinline__ void run_sum(uint64_t y, uint64_t cnt, uint64_t key, 
         for (int u = 0; u < U; ++u) {
           const uint64_t z = y + key;
           unsigned long long c;
-          s = __builtin_addcll(s, sum_term<K>(y, z), 0ull, &c);
+          s = __builtin_addcll(s, sum_term_after1<K>(r1, y, z), 0ull, &c);
           carries += (uint32_t)c;
+          r1 += d;
+          d += k.dd;
           y = next_y<S>(y, z, dkey);
         }
       }
       for (; j < len; ++j) {
         const uint64_t z = y + key;
         unsigned long long c;
-        s = __builtin_addcll(s, sum_term<K>(y, z), 0ull, &c);
+        s = __builtin_addcll(s, sum_term_after1<K>(r1, y, z), 0ull, &c);
         carries += (uint32_t)c;
+        r1 += d;
+        d += k.dd;
         y = next_y<S>(y, z, dkey);
       }
       add128(lo, hi, s, carries);
@@ -266,13 +275,17 @@ __device__ __forceinline__ void run_sum(uint64_t y, uint64_t cnt, uint64_t key, 
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const uint64_t z = y + key;
-          s += (Part)sum_term<K>(y, z);
+          s += (Part)sum_term_after1<K>(r1, y, z);
+          r1 += d;
+          d += k.dd;
           y = next_y<S>(y, z, dkey);
         }
       }
       for (; j < len; ++j) {
         const uint64_t z = y + key;
-        s += (Part)sum_term<K>(y, z);
+        s += (Part)sum_term_after1<K>(r1, y, z);
+        r1 += d;
+        d += k.dd;
         y = next_y<S>(y, z, dkey);
       }
       add128(lo, hi, (uint64_t)s, 0);
@@ -361,6 +374,8 @@ __device__ __forceinline__ void pair_terms(uint64_t v, typename std::conditional
 template <int P, int U>
 __device__ __forceinline__ void run_sum_pair(uint64_t y, uint64_t cnt, uint64_t key, uint64_t& lo32,
                                              uint64_t& hi32, uint64_t& lo64, uint64_t& hi64) {
+  const FdConst k = fd_const(opaque_uniform(key));
+  uint64_t r1 = square_plus(y, y), d = fd_diff(y, k);
   // F32 terms < 2^24: 256 fit a 32-bit partial; F64 terms < 2^53: 256 fit
   // 64 bits.  U32 terms < 2^32: 2^20 fit 64 bits; U64 terms count carries.
   constexpr uint32_t FLUSH = P == 1 ? 256u : (1u << 20);
@@ -377,13 +392,17 @@ __device__ __forceinline__ void run_sum_pair(uint64_t y, uint64_t cnt, uint64_t 
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const uint64_t z = y + key;
-        pair_terms<P>(sq64(y, z), s32, s64, carries);
+        pair_terms<P>(sq64_after1(r1, y, z), s32, s64, carries);
+        r1 += d;
+        d += k.dd;
         y = z;
       }
     }
     for (; j < len; ++j) {
       const uint64_t z = y + key;
-      pair_terms<P>(sq64(y, z), s32, s64, carries);
+      pair_terms<P>(sq64_after1(r1, y, z), s32, s64, carries);
+      r1 += d;
+      d += k.dd;
       y = z;
     }
     add128(lo32, hi32, (uint64_t)s32, 0);
@@ -549,13 +568,55 @@ __global__ __launch_bounds__(256) void k_batch_map(const sqi::BatchHdr* hdr, con
   }
 }
 
+// Sixteen bytes of consecutive outputs of kind K from the first Weyl term
+// y0 and round 1's running-difference state (r1, d) at y0 (fd_const of
+// key): round 1 of the vector's later counters comes from r1 += d,
+// d += 2*key*key instead of squarings.
+template <int K>
+__device__ __forceinline__ u32x4 gen_vec_fd(uint64_t y0, uint64_t key, uint64_t r1, uint64_t d, uint64_t dd) {
+  u32x4 o;
+  if constexpr (Kind<K>::CPV == 4) {
+    const uint64_t y1 = y0 + key, y2 = y1 + key, y3 = y2 + key, y4 = y3 + key;
+    const uint64_t r1b = r1 + d, d1 = d + dd, r1c = r1b + d1, r1d = r1c + (d1 + dd);
+    uint32_t v[4];
+    v[0] = sq32_after1(r1, y0, y1);
+    v[1] = sq32_after1(r1b, y1, y2);
+    v[2] = sq32_after1(r1c, y2, y3);
+    v[3] = sq32_after1(r1d, y3, y4);
+    if constexpr (K == 1) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v[j] = __float_as_uint(to_f32(v[j]));
+    }
+    o.x = v[0]; o.y = v[1]; o.z = v[2]; o.w = v[3];
+  } else {
+    const uint64_t y1 = y0 + key, y2 = y1 + key;
+    uint64_t a = sq64_after1(r1, y0, y1), b = sq64_after1(r1 + d, y1, y2);
+    if constexpr (K == 3) {
+      a = (uint64_t)__double_as_longlong(to_f64(a));
+      b = (uint64_t)__double_as_longlong(to_f64(b));
+    }
+    if constexpr (K == 5) {
+      o.x = __float_as_uint(to_f32((uint32_t)a)); o.y = __float_as_uint(to_f32((uint32_t)(a >> 32)));
+      o.z = __float_as_uint(to_f32((uint32_t)b)); o.w = __float_as_uint(to_f32((uint32_t)(b >> 32)));
+    } else {
+      o.x = (uint32_t)a; o.y = (uint32_t)(a >> 32);
+      o.z = (uint32_t)b; o.w = (uint32_t)(b >> 32);
+    }
+  }
+  return o;
+}
+
 // The workgroup fills `cnt` outputs of kind K from counter ctr at p
 // (element-aligned, workgroup-uniform): a head up to the next 1 KiB boundary
 // and a tail, element stores, and in between chunks of B*U 16-byte vectors
 // laid out as in the plain fill (each store instruction of a wave covers one
 // aligned KiB).  A tile holds at most 2^24 outputs, so its vector counts fit
-// 32 bits.  The lane's Weyl offset tid*ekey is computed once per tile; a
-// chunk adds it to the chunk's uniform Weyl term (one 64-bit add) and the
+// 32 bits.  Lane tid owns vectors tid, tid + B, tid + 2B, ...: their first
+// Weyl terms are B*ekey apart, so the lane carries its Weyl term and round
+// 1's running differences from one vector to the next (fd_const along the
+// key within a vector, along B*ekey between the lane's vectors): per vector
+// that is four 64-bit adds instead of the squarings of its first counter
+// and one 64-bit multiply; the lane's state is set up once per tile.  The
 // stores add the lane's 32-bit offset to the chunk's uniform address.
 // Lanes 0..B-1 of the workgroup take part.
 template <int K, int U>
@@ -571,29 +632,42 @@ __device__ __forceinline__ void fill_range(uint64_t key, uint64_t ctr, uint64_t 
     const uint64_t i = t < head ? t : head + (uint64_t)nvec * E + (t - head);
     store_elem<K>(p + i * W, ctr, i, key);
   }
+  if (tid >= nvec) return;  // no vector for this lane (also covers nvec == 0)
   unsigned char* body = p + (uint64_t)head * W;
   const uint64_t ekey = (uint64_t)Kind<K>::CPV * key;
+  const uint64_t ystep = (uint64_t)B * ekey;  // Weyl step from one of the lane's vectors to its next
   const uint64_t y_body = (ctr + elem_ctr<K>(head)) * key;  // head is even for split kinds
-  const uint64_t lane_y = lane_weyl(0, ekey, tid);
-  const uint64_t ystep = (uint64_t)B * ekey;
+  // the lane's first vector, and round 1's differences along the key
+  // (within a vector) and along ystep (from vector to vector); between
+  // vectors the key difference itself moves by 2*key*ystep
+  const FdConst kc = fd_const(opaque_uniform(key)), kv = fd_const(opaque_uniform(ystep));
+  const uint64_t dmove = opaque_uniform(kc.s2 * ystep);
+  uint64_t y = opaque(lane_weyl(y_body, ekey, tid));
+  uint64_t r1 = square_plus(y, y), d = fd_diff(y, kc), D = fd_diff(y, kv);
   const uint32_t per_chunk = B * U;
 #pragma unroll 1
   for (uint32_t c0 = 0; c0 < nvec; c0 += per_chunk) {
-    uint64_t y = opaque(opaque_uniform(y_body + c0 * ekey) + lane_y);
     unsigned char* base = body + (uint64_t)c0 * 16;
     if (c0 + per_chunk <= nvec) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        *(u32x4*)(base + (uint64_t)u * B * 16 + tid * 16u) = gen_vec<K>(y, key);
+        *(u32x4*)(base + (uint64_t)u * B * 16 + tid * 16u) = gen_vec_fd<K>(y, key, r1, d, kc.dd);
         y += ystep;
+        r1 += D;
+        D += kv.dd;
+        d += dmove;
         __builtin_amdgcn_sched_barrier(0);
       }
     } else {
       const uint32_t rem = nvec - c0;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        if (tid + (uint32_t)u * B < rem) *(u32x4*)(base + (uint64_t)u * B * 16 + tid * 16u) = gen_vec<K>(y, key);
+        if (tid + (uint32_t)u * B < rem)
+          *(u32x4*)(base + (uint64_t)u * B * 16 + tid * 16u) = gen_vec_fd<K>(y, key, r1, d, kc.dd);
         y += ystep;
+        r1 += D;
+        D += kv.dd;
+        d += dmove;
         __builtin_amdgcn_sched_barrier(0);
       }
     }
