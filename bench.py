@@ -79,13 +79,20 @@ def traffic_from_pmc(fetch_csv: str, write_csv: str, log2n: int) -> dict:
     import csv
     import re
 
+    pats = dict(KERNEL_NAMES)
+    pats["batch_fill"] = r"k_batch_fill<\d+>"
+
     def load(path):
         rows = list(csv.DictReader(open(path)))
         copy = max((r for r in rows if "copyBuffer" in r["Kernel_Name"]), key=lambda r: float(r["Counter_Value"]))
         per = {}
-        for name, pat in KERNEL_NAMES.items():
+        for name, pat in pats.items():
+            # fills: only the 2^32-output launches (one workgroup per 4 KiB chunk,
+            # at least 2^30 work-items), not the batch extra's per-stream launches
             vals = [float(r["Counter_Value"]) * 1024 for r in rows
-                    if re.search(pat, r["Kernel_Name"].replace(" ", "").replace("(anonymousnamespace)::", ""))]
+                    if re.search(pat, r["Kernel_Name"].replace(" ", "").replace("(anonymousnamespace)::", ""))
+                    and (not name.endswith("_fill") or name == "batch_fill"
+                         or int(r.get("Grid_Size") or (1 << 31)) >= (1 << 30))]
             per[name] = sum(vals) / len(vals) if vals else None
         return float(copy["Counter_Value"]) * 1024, per
 
@@ -94,7 +101,7 @@ def traffic_from_pmc(fetch_csv: str, write_csv: str, log2n: int) -> dict:
     ref = float(4 << 30)
     ff, fw = ref / copy_f, ref / copy_w
     kernels, detail = {}, {}
-    for name in KERNEL_NAMES:
+    for name in pats:
         if fetch[name] is None or write[name] is None:
             continue
         kernels[name] = round(fetch[name] * ff + write[name] * fw)
@@ -190,6 +197,40 @@ def valu_from_pmc(csv_path: str, log2n: int) -> dict:
     return {"source_sha": kernel_source_sha(), "log2n": log2n, "kernels": kernels}
 
 
+def kernel_summary(trace_csv: str) -> str:
+    """Markdown table of the full-size dispatches of the step kernels, the
+    uniform fills and the store ceiling (at least 2^30 work-items: one
+    workgroup per 4 KiB chunk of a 2^32-output fill; the per-stream launches
+    of the batch extras use the same fill instantiations on far smaller
+    grids and are left out), of the sums, and of the batch fill's dispatches
+    that take at least 1 ms (the 4096- and 65536-stream batches) in a
+    rocprofv3 --kernel-trace csv of this benchmark."""
+    import csv
+    import re
+
+    pats = dict(KERNEL_NAMES)
+    pats.update({"uniform_f32_fill": r"k_fill<1,\d+,false>", "uniform_f64_fill": r"k_fill<3,\d+,false>",
+                 "store_ceiling": r"k_store_chunk", "batch_fill": r"k_batch_fill<\d+>"})
+    rows = {k: [] for k in pats}
+    for r in csv.DictReader(open(trace_csv)):
+        name = r["Kernel_Name"].replace(" ", "").replace("(anonymousnamespace)::", "")
+        grid = int(r.get("Grid_Size", r.get("Grid_Size_X", 0)) or 0)
+        ms = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
+        for k, pat in pats.items():
+            if not re.search(pat, name):
+                continue
+            if ("fill" in k or k == "store_ceiling") and k != "batch_fill" and grid < (1 << 30):
+                continue
+            if k == "batch_fill" and ms < 1.0:
+                continue
+            rows[k].append(ms)
+    out = ["| Kernel | Dispatches | Average (ms) | Min (ms) | Max (ms) |", "|---|---|---|---|---|"]
+    for k, v in rows.items():
+        if v:
+            out.append(f"| {k} | {len(v)} | {sum(v) / len(v):.4f} | {min(v):.4f} | {max(v):.4f} |")
+    return "\n".join(out)
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -205,6 +246,8 @@ def parse():
                    help="run a plain 4 GiB device copy first (scales HBM byte counters)")
     p.add_argument("--traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                    help="write profiles/traffic.json from two rocprofv3 --pmc counter_collection.csv files")
+    p.add_argument("--kernel-summary", metavar="TRACE_CSV",
+                   help="print a table of the full-size kernel dispatches in a rocprofv3 --kernel-trace csv")
     p.add_argument("--valu", metavar="PMC_CSV",
                    help="write profiles/valu.json from a rocprofv3 --pmc GRBM_GUI_ACTIVE SQ_INSTS_VALU "
                         "counter_collection.csv of this benchmark")
@@ -535,6 +578,9 @@ def counter_modes(sq, torch, key: int, ctr0: int, n: int, per_op_ms: dict) -> di
 
 def main() -> int:
     args = parse()
+    if args.kernel_summary:
+        print(kernel_summary(args.kernel_summary))
+        return 0
     if args.valu:
         t = valu_from_pmc(args.valu, args.log2n)
         with open(os.path.join(ROOT, "profiles", "valu.json"), "w") as f:

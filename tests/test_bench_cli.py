@@ -53,3 +53,37 @@ def test_traffic_extraction_scales_by_the_copy(tmp_path):
     assert t["kernels"]["sq64_fill"] == 32 * 1024 + (32 << 30)
     assert t["kernels"]["fused_f32_sum"] == 35 * 1024 + 2176 * 1024
     assert t["source_sha"] == bench.kernel_source_sha()
+
+
+def test_kernel_summary_keeps_full_size_dispatches(tmp_path):
+    import bench
+
+    p = str(tmp_path / "trace.csv")
+    with open(p, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Grid_Size", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        big, small = 1 << 31, 1 << 22
+        for name, grid, ns in [("void (anonymous namespace)::k_fill<2, 1, false>(FillArgs)", big, 4_800_000),
+                               ("void (anonymous namespace)::k_fill<2, 1, false>(FillArgs)", big, 4_600_000),
+                               ("void (anonymous namespace)::k_fill<2, 1, false>(FillArgs)", small, 3_000),
+                               ("void (anonymous namespace)::k_fill<0, 1, false>(FillArgs)", 1 << 30, 2_500_000),
+                               ("void (anonymous namespace)::k_store_chunk(unsigned char*, unsigned int, unsigned int)",
+                                big, 5_000_000)]:
+            w.writerow({"Kernel_Name": name, "Grid_Size": grid, "Start_Timestamp": 1000, "End_Timestamp": 1000 + ns})
+    s = bench.kernel_summary(p)
+    assert "| sq64_fill | 2 | 4.7000 | 4.6000 | 4.8000 |" in s
+    assert "| sq32_fill | 1 | 2.5000 |" in s
+    assert "| store_ceiling | 1 | 5.0000 |" in s
+
+
+def test_clock_from_samples():
+    import numpy as np
+
+    import bench
+
+    # shader clock counter at 2.0 GHz against the 100 MHz real-time counter
+    wall = np.arange(0, 100_000, 1000, dtype=np.uint64)
+    clk = wall * np.uint64(20) + np.uint64(12345)
+    raw = np.stack([clk, wall], axis=1).reshape(-1)
+    c = bench.clock_from_samples(raw)
+    assert c["mean_ghz"] == 2.0 and c["p10_ghz"] == 2.0 and c["samples"] == 100
