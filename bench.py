@@ -525,11 +525,11 @@ def concurrent_step(sq, torch, key: int, ctr0: int, n: int, serial_ms: float, st
 def uniform_fills(sq, torch, key: int, ctr0: int, n: int, valu: dict | None = None) -> dict:
     """The uniform fills over the same n counters: F32 (16 GiB) and F64
     (32 GiB), conversion fused into the generating kernel, back to back
-    (mean of 10 after 2)."""
+    (mean of 20 after 8, as the steady rooflines)."""
     r = {}
     for name, kind, W in (("uniform_f32", sq.F32, 4), ("uniform_f64", sq.F64, 8)):
         out = torch.empty(n * W, dtype=torch.uint8, device="cuda")
-        ms = _event_ms(torch, lambda: sq.fill(kind, key, ctr0, n, out=out))
+        ms = _event_ms(torch, lambda: sq.fill(kind, key, ctr0, n, out=out), reps=20, warm=8)
         gbs = W * n / (ms * 1e-3) / 1e9
         r[name] = {"n": n, "ms": round(ms, 4), "gnum_s": round(n / (ms * 1e-3) / 1e9, 1), "gb_s": round(gbs, 1),
                    "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
@@ -735,11 +735,11 @@ def main() -> int:
         "fused_f32_sum": alu_roof("fused_f32_sum", SLOTS["sq32"] + SLOTS["sum_f32"]),
         "fused_f64_sum": alu_roof("fused_f64_sum", SLOTS["sq64"] + SLOTS["sum_f64"]),
     }
-    # The same kernels repeated back to back (10 timed after 3 untimed): in the
-    # step, a kernel that follows one of the other class starts while the
-    # shader clock is still moving between the memory-bound and the
-    # compute-bound operating points, which costs up to ~0.5 ms per switch.
-    steady_ms = {name: _event_ms(torch, fn, reps=10, warm=3) for name, fn in ops}
+    # The same kernels repeated back to back (20 timed after 8 untimed): in the
+    # step, a kernel that follows one of the other class meets the shader
+    # clock of the other operating point, and the clock moves to its own over
+    # tens of milliseconds (a dozen launches), so the warm-up covers that.
+    steady_ms = {name: _event_ms(torch, fn, reps=20, warm=8) for name, fn in ops}
     rooflines_steady = {
         "sq32_fill": hbm_roof("sq32_fill", 4 * n, steady_ms),
         "sq64_fill": hbm_roof("sq64_fill", 8 * n, steady_ms),
