@@ -57,7 +57,7 @@ SLOTS = {
 KERNEL_SOURCES = ["paper_2004_06278_amd/csrc/sq_device.hpp", "paper_2004_06278_amd/csrc/sq_kernels.hip"]
 # rocprofv3 kernel names (spaces and namespace removed) of the four step
 # operations: the unit-step instantiations of the fill and reduce templates
-KERNEL_NAMES = {"sq32_fill": r"k_fill<0,\d+,false>", "sq64_fill": r"k_fill<2,\d+,false>",
+KERNEL_NAMES = {"sq32_fill": r"k_fill(_lanes)?<0,(\d+,)?false>", "sq64_fill": r"k_fill(_lanes)?<2,(\d+,)?false>",
                 "fused_f32_sum": r"k_reduce(_queue)?<1,\d+,false>", "fused_f64_sum": r"k_reduce(_queue)?<3,\d+,false>"}
 
 
@@ -173,7 +173,8 @@ def valu_from_pmc(csv_path: str, log2n: int) -> dict:
 
     n = 1 << log2n
     pats = dict(KERNEL_NAMES)
-    pats.update({"uniform_f32_fill": r"k_fill<1,\d+,false>", "uniform_f64_fill": r"k_fill<3,\d+,false>",
+    pats.update({"uniform_f32_fill": r"k_fill(_lanes)?<1,(\d+,)?false>",
+                 "uniform_f64_fill": r"k_fill(_lanes)?<3,(\d+,)?false>",
                  "batch_fill": r"k_batch_fill<\d+>"})
     outputs = {k: n for k in pats}
     outputs["batch_fill"] = W.ragged_batch(seed=3).total_outputs
@@ -209,7 +210,8 @@ def kernel_summary(trace_csv: str) -> str:
     import re
 
     pats = dict(KERNEL_NAMES)
-    pats.update({"uniform_f32_fill": r"k_fill<1,\d+,false>", "uniform_f64_fill": r"k_fill<3,\d+,false>",
+    pats.update({"uniform_f32_fill": r"k_fill(_lanes)?<1,(\d+,)?false>",
+                 "uniform_f64_fill": r"k_fill(_lanes)?<3,(\d+,)?false>",
                  "store_ceiling": r"k_store_chunk", "batch_fill": r"k_batch_fill<\d+>"})
     rows = {k: [] for k in pats}
     for r in csv.DictReader(open(trace_csv)):
@@ -242,6 +244,9 @@ def parse():
                    help="comma list of extra measurements after the step "
                         "(concurrent, uniform, pair, split, modes, batch, batch_wrap, serving)")
     p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--no-per-stream", action="store_true",
+                   help="batch extra without its 4096 per-stream launches (counter-collection runs, which need "
+                        "only the batch kernels)")
     p.add_argument("--calib-copy", action="store_true",
                    help="run a plain 4 GiB device copy first (scales HBM byte counters)")
     p.add_argument("--traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -310,11 +315,12 @@ def timed_wall(torch, fn, reps: int, warm: int = 2) -> float:
     return (time.perf_counter() - t0) / reps
 
 
-def batch_speedup(sq, torch) -> dict:
+def batch_speedup(sq, torch, per_stream_baseline: bool = True) -> dict:
     """4096 keys, log-uniform lengths in [2^10, 2^24], U32/F32: replays of the
     captured batch plan (scan, map and fill kernels) against the same batch as
     4096 separate fill launches on one stream, each timed per call over calls
-    issued back to back (timed_wall)."""
+    issued back to back (timed_wall).  per_stream_baseline=False skips the
+    4096 launches (counter-collection runs need only the batch kernels)."""
     from paper_2004_06278_amd import workloads as W
 
     b = W.ragged_batch(seed=3)
@@ -328,7 +334,7 @@ def batch_speedup(sq, torch) -> dict:
         return timed_wall(torch, fn, reps)
 
     t_plan = timed(plan.launch, 10)
-    t_each = timed(per_stream, 4)
+    t_each = timed(per_stream, 4) if per_stream_baseline else None
     plan.close()
     n = b.total_outputs
     del db
@@ -341,11 +347,14 @@ def batch_speedup(sq, torch) -> dict:
     planm.close()
     del dbm
     torch.cuda.empty_cache()
-    return {"workload": "4096 keys, log-uniform lengths 2^10..2^24, U32/F32", "outputs": n,
-            "graph_ms": round(t_plan * 1e3, 3), "per_stream_ms": round(t_each * 1e3, 3),
-            "graph_gnum_s": round(n / t_plan / 1e9, 1), "per_stream_gnum_s": round(n / t_each / 1e9, 1),
-            "speedup": round(t_each / t_plan, 2), "graph_gb_s": round(4 * n / t_plan / 1e9, 1),
-            "misaligned_graph_ms": round(t_mis * 1e3, 3)}
+    r = {"workload": "4096 keys, log-uniform lengths 2^10..2^24, U32/F32", "outputs": n,
+         "graph_ms": round(t_plan * 1e3, 3), "per_stream_ms": None, "graph_gnum_s": round(n / t_plan / 1e9, 1),
+         "per_stream_gnum_s": None, "speedup": None, "graph_gb_s": round(4 * n / t_plan / 1e9, 1),
+         "misaligned_graph_ms": round(t_mis * 1e3, 3)}
+    if t_each is not None:
+        r.update({"per_stream_ms": round(t_each * 1e3, 3), "per_stream_gnum_s": round(n / t_each / 1e9, 1),
+                  "speedup": round(t_each / t_plan, 2)})
+    return r
 
 
 def batch_wrap_speedup(sq, torch) -> dict:
@@ -798,7 +807,7 @@ def main() -> int:
     if "modes" in extras:
         line["counter_modes"] = counter_modes(sq, torch, key, ctr0, n, per_op_ms)
     if "batch" in extras:
-        line["batch"] = batch_speedup(sq, torch)
+        line["batch"] = batch_speedup(sq, torch, per_stream_baseline=not args.no_per_stream)
         if "batch_fill" in valu:
             line["batch"]["valu_instr_per_output_measured"] = valu["batch_fill"]["valu_instr_per_output"]
     if "batch_wrap" in extras:

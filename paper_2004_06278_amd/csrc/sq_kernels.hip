@@ -10,6 +10,7 @@
 // fastest launch gives each workgroup one 4 KiB chunk).  The reduce writes
 // nothing per element; it is bound by the VALU issue rate.
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include <algorithm>
@@ -22,6 +23,15 @@
 #include "sq_internal.hpp"
 
 using namespace sqd;
+
+// Structured-buffer load and store (the LLVM intrinsics, declared under
+// their own names): the address is the descriptor's base plus
+// vindex * stride, so a lane index needs no address arithmetic.
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+__device__ u32x2 buffer_load_idx_v2(__amdgpu_buffer_rsrc_t rsrc, int vindex, int voffset, int soffset,
+                                    int aux) __asm("llvm.amdgcn.struct.ptr.buffer.load.v2i32");
+__device__ void buffer_store_idx_v4(u32x4 vdata, __amdgpu_buffer_rsrc_t rsrc, int vindex, int voffset, int soffset,
+                                    int aux) __asm("llvm.amdgcn.struct.ptr.buffer.store.v4i32");
 
 namespace {
 
@@ -130,6 +140,62 @@ __global__ __launch_bounds__(1024) void k_fill(FillArgs a) {
 #pragma unroll 1
     for (uint32_t c = beg + local; c < end; c += gx)
       fill_chunk<K, U, S>(a, c, opaque(opaque_uniform(a.y_body + c * cw) + lane_y));
+  }
+}
+
+// The one-chunk shape with one vector per lane (the fastest fill launch:
+// 256 lanes, one 16-byte vector each) in the fewest instructions.  Its lane
+// setup, the first Weyl term yc + tid*ekey and the store address, would take
+// five VALU instructions per lane, spread over only four (or two) outputs.
+// Here the host puts tid*ekey for every lane into the kernel arguments; each
+// lane reads its entry with one structured-buffer load (index = tid, no
+// address arithmetic), issued first so that its latency overlaps the
+// scalar set-up, and adds the chunk's term in one 64-bit add; the vector is
+// written with a structured-buffer store whose index is tid again.  The
+// store is the lane's last instruction, so no later instruction can
+// overwrite its data registers before the store has read them.  The block
+// size is a compile-time constant: read from the dispatch, it would put a
+// scalar load in front of the table load.
+constexpr uint32_t kLaneBlock = 256;
+constexpr uint64_t kLaneMinVec = 1ull << 22;  // 64 MiB of output
+struct FillLaneArgs {
+  uint64_t lane[kLaneBlock];  // lane[t] = t * ekey; first, so it starts the argument segment
+  FillArgs a;
+};
+static_assert(offsetof(FillLaneArgs, lane) == 0, "the lane table starts the kernel arguments");
+
+// Word 3 of a buffer descriptor: 32-bit data format (any valid one serves
+// untyped dword loads and stores).
+constexpr int kRsrcWord3 = 0x00020000;
+
+template <int K, bool S>
+__global__ __launch_bounds__(kLaneBlock) void k_fill_lanes(FillLaneArgs t) {
+  const uint32_t c = blockIdx.x, tid = threadIdx.x;
+  // the kernel's only argument starts the kernel-argument segment
+  const auto tab = __builtin_amdgcn_make_buffer_rsrc((void*)__builtin_amdgcn_kernarg_segment_ptr(), (short)8,
+                                                     (int)kLaneBlock, kRsrcWord3);
+  const u32x2 off = buffer_load_idx_v2(tab, (int)tid, 0, 0, 0);
+  const FillArgs& a = t.a;
+  fill_edges<K>(a);
+  if (c >= a.nchunks) return;
+  const uint64_t yc = opaque_uniform(a.y_body + c * ((uint64_t)kLaneBlock * a.ekey));
+  const uint64_t y = yc + (((uint64_t)off.y << 32) | off.x);
+  const auto out = __builtin_amdgcn_make_buffer_rsrc(a.body + (uint64_t)c * (kLaneBlock * 16), (short)16,
+                                                     (int)kLaneBlock, kRsrcWord3);
+  if (c < a.full) buffer_store_idx_v4(body_vec<K, S>(a, y), out, (int)tid, 0, 0, 0);
+  else if (tid < a.rem) buffer_store_idx_v4(body_vec<K, S>(a, y), out, (int)tid, 0, 0, 0);
+}
+
+typedef void (*FillLanesKernel)(FillLaneArgs);
+template <bool S>
+FillLanesKernel fill_lanes_kernel(int kind) {
+  switch (kind) {
+    case SQ_U32: return k_fill_lanes<0, S>;
+    case SQ_F32: return k_fill_lanes<1, S>;
+    case SQ_U64: return k_fill_lanes<2, S>;
+    case SQ_F64: return k_fill_lanes<3, S>;
+    case SQ_U32X2: return k_fill_lanes<4, S>;
+    default: return k_fill_lanes<5, S>;
   }
 }
 
@@ -973,7 +1039,16 @@ hipError_t launch_fill(int kind, uint64_t key, uint64_t ctr0, uint64_t n, void* 
   const uint64_t per_chunk = (uint64_t)cfg.block * cfg.unroll;
   std::vector<FillSegment> segs;
   plan_fill(nvec, cfg, (uint32_t)device_info().cus, segs);
+  // One chunk of one vector per lane per workgroup: the lane-table kernel,
+  // for bodies of at least kLaneMinVec vectors.  Its 2 KiB of arguments cost
+  // the host about 0.7 us more per launch, which small fills (whose kernels
+  // take microseconds) would feel and large ones do not.
+  const bool lanes = cfg.xcd_map == 2 && cfg.unroll == 1 && cfg.block == kLaneBlock && nvec >= kLaneMinVec;
+  FillLaneArgs t;
+  if (lanes)
+    for (uint32_t i = 0; i < kLaneBlock; ++i) t.lane[i] = i * a.ekey;
   const FillKernel k = step == 1 ? fill_kernel<false>(kind, cfg.unroll) : fill_kernel<true>(kind, cfg.unroll);
+  const FillLanesKernel kl = step == 1 ? fill_lanes_kernel<false>(kind) : fill_lanes_kernel<true>(kind);
   for (size_t i = 0; i < segs.size(); ++i) {
     const FillSegment& g = segs[i];
     a.body = body + g.first_chunk * per_chunk * 16;
@@ -983,7 +1058,12 @@ hipError_t launch_fill(int kind, uint64_t key, uint64_t ctr0, uint64_t n, void* 
     a.rem = g.rem;
     a.xcd_map = g.xcd_map;
     a.edges = i == 0;
-    hipLaunchKernelGGL(k, dim3(g.grid), dim3(cfg.block), 0, s, a);
+    if (lanes) {
+      t.a = a;
+      hipLaunchKernelGGL(kl, dim3(g.grid), dim3(cfg.block), 0, s, t);
+    } else {
+      hipLaunchKernelGGL(k, dim3(g.grid), dim3(cfg.block), 0, s, a);
+    }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

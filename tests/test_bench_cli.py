@@ -34,14 +34,16 @@ def test_traffic_extraction_scales_by_the_copy(tmp_path):
     copy = "__amd_rocclr_copyBuffer"
     GiB_KiB = 1 << 20
     # the copy of 4 GiB reads 2x its size on the fetch counter and 1x on the write counter
-    fetch = [(copy, 1024.0), (copy, 8 * GiB_KiB), ("void (anonymous namespace)::k_fill<0, 1, false>(FillArgs)", 20.0),
+    # the one-chunk fills run as k_fill_lanes<K, S>, the other shapes as k_fill<K, U, S>
+    lanes0 = "void (anonymous namespace)::k_fill_lanes<0, false>(FillLaneArgs)"
+    lanes2 = "void (anonymous namespace)::k_fill_lanes<2, false>(FillLaneArgs)"
+    fetch = [(copy, 1024.0), (copy, 8 * GiB_KiB), (lanes0, 20.0),
              ("void (anonymous namespace)::k_fill<0, 1, false>(FillArgs)", 40.0),
-             ("void (anonymous namespace)::k_fill<2, 1, false>(FillArgs)", 64.0),
+             (lanes2, 64.0),
              ("void (anonymous namespace)::k_reduce_queue<1, 2, false>(ReduceArgs)", 70.0),
              ("void (anonymous namespace)::k_reduce_queue<3, 2, false>(ReduceArgs)", 72.0),
              ("void (anonymous namespace)::k_fill<0, 4, true>(FillArgs)", 9999.0)]  # strided: not a step kernel
-    write = [(copy, 4 * GiB_KiB), ("void (anonymous namespace)::k_fill<0, 1, false>(FillArgs)", 16 * GiB_KiB),
-             ("void (anonymous namespace)::k_fill<2, 1, false>(FillArgs)", 32 * GiB_KiB),
+    write = [(copy, 4 * GiB_KiB), (lanes0, 16 * GiB_KiB), (lanes2, 32 * GiB_KiB),
              ("void (anonymous namespace)::k_reduce_queue<1, 2, false>(ReduceArgs)", 2176.0),
              ("void (anonymous namespace)::k_reduce_queue<3, 2, false>(ReduceArgs)", 2176.0)]
     fp, wp = str(tmp_path / "fetch.csv"), str(tmp_path / "write.csv")
@@ -63,7 +65,7 @@ def test_kernel_summary_keeps_full_size_dispatches(tmp_path):
         w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Grid_Size", "Start_Timestamp", "End_Timestamp"])
         w.writeheader()
         big, small = 1 << 31, 1 << 22
-        for name, grid, ns in [("void (anonymous namespace)::k_fill<2, 1, false>(FillArgs)", big, 4_800_000),
+        for name, grid, ns in [("void (anonymous namespace)::k_fill_lanes<2, false>(FillLaneArgs)", big, 4_800_000),
                                ("void (anonymous namespace)::k_fill<2, 1, false>(FillArgs)", big, 4_600_000),
                                ("void (anonymous namespace)::k_fill<2, 1, false>(FillArgs)", small, 3_000),
                                ("void (anonymous namespace)::k_fill<0, 1, false>(FillArgs)", 1 << 30, 2_500_000),

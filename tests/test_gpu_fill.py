@@ -94,6 +94,37 @@ def test_fill_misaligned_every_order(sq, oracle_mod, kind):
                 assert np.all(host[: 64 + off] == 0x3C) and np.all(host[64 + off + n * W:] == 0x3C)
 
 
+@pytest.mark.parametrize("kind", KINDS)
+def test_fill_lanes_shape_ragged_misaligned(sq, oracle_mod, kind):
+    """Bodies of at least 2^22 16-byte vectors in the one-vector-per-lane
+    shape (256 lanes, one chunk per workgroup) take the kernel that reads each
+    lane's Weyl offset from its argument table: a ragged size (a partial last
+    chunk and a tail of single elements) at start offsets that leave a head,
+    with counters that wrap past 2^64, equals the oracle and writes nothing
+    outside its range."""
+    import torch
+
+    W, A = KIND_BYTES[kind], KIND_ALIGN[kind]
+    E = 16 // W
+    n = E * ((1 << 22) + 3 * 256 + 3) + (E - 1)
+    key, ctr0 = 0x7C1F4A9E3B5D2068, 2**64 - 5 * 10**6
+    ref = oracle_bytes(oracle_mod, kind, key, ctr0, n)
+    buf = torch.empty(n * W + 4096, dtype=torch.uint8, device="cuda")
+    c = sq.cfg(256, 1, 1, 2)
+    for off in (A, 1024 - A, 0):
+        log(f"lanes-shape fill kind={kind} n={n} off={off}")
+        buf.fill_(0x5E)
+        sq.check(sq.lib().sq_fill_cfg(kind, key, ctr0, n, buf.data_ptr() + 1024 + off, sq.ctypes.byref(c),
+                                      sq._stream()))
+        torch.cuda.synchronize()
+        host = to_host_bytes(buf)
+        got = host[1024 + off: 1024 + off + n * W]
+        assert got.tobytes() == ref.tobytes(), first_diff(got, ref)
+        assert np.all(host[: 1024 + off] == 0x5E) and np.all(host[1024 + off + n * W:] == 0x5E)
+    del buf
+    torch.cuda.empty_cache()
+
+
 def test_invalid_arguments(sq):
     import torch
 

@@ -80,6 +80,23 @@ def test_strided_step_one_is_the_fill(sq, kind):
     assert a.tobytes() == b.tobytes()
 
 
+@pytest.mark.parametrize("kind", [0, 1, 2, 3, 4, 5])
+def test_strided_lanes_shape_complete(sq, oracle_mod, kind):
+    """A strided fill of at least 2^22 16-byte vectors in the one-vector-per-
+    lane shape (the lane-table kernel), ragged and with counters wrapping past
+    2^64, for a small step and one above 2^32: every output equals the
+    oracle's."""
+    E = 16 // KIND_BYTES[kind]
+    n = E * ((1 << 22) + 5 * 256 + 1) + (E - 1)
+    key = 0x3D9B1F6A58C2E407
+    c = sq.cfg(256, 1, 1, 2)
+    for step, ctr0 in ((3, 2**64 - 7 * 10**6), (2**32 + 1, 0x9E3779B97F4A7C15)):
+        log(f"strided lanes-shape kind={kind} step={step:#x} n={n}")
+        got = to_host_bytes(sq.fill_strided(kind, key, ctr0, step, n, launch_cfg=c))
+        ref = oracle_mod.fill_strided(kind, key, ctr0, step, n).view(np.uint8)
+        assert got.tobytes() == ref.tobytes(), first_diff(got, ref)
+
+
 def test_strided_large_sampled(sq, oracle_mod):
     """2^28 squares32 outputs with step 3 from a random counter: first, last and
     4096 random outputs equal the oracle's."""
