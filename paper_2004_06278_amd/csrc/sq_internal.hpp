@@ -89,6 +89,14 @@ struct FillSegment {
   uint32_t xcd_map;      // chunk order actually used (1 falls back to 0 below 8 workgroups)
 };
 uint32_t max_segment_chunks(uint32_t block);
+// The largest grid of `block`-lane workgroups below 2^32 work-items (and
+// 2^31 workgroups), the launch limit the HIP headers state.  Host code, like the two grids below: key-counter mode
+// over `work` vectors or keys (one per lane where the grid allows, else a
+// grid-stride loop), and the batch fill over at most `tiles_bound` tiles
+// (one per workgroup in order 2, else a persistent grid).
+uint32_t grid_cap(uint32_t block);
+uint32_t keys_grid(uint64_t work, const sq_launch_cfg& cfg, uint32_t cus);
+uint32_t batch_grid(uint64_t tiles_bound, const sq_launch_cfg& cfg, uint32_t cus);
 void plan_fill(uint64_t nvec, const sq_launch_cfg& cfg, uint32_t cus, std::vector<FillSegment>& segs);
 
 // step: counter increment between consecutive outputs (1 for the plain

@@ -976,9 +976,25 @@ __global__ __launch_bounds__(256) void k_make_keys(uint64_t gen_key, uint64_t ct
 // ============================================================== launchers
 namespace sqi {
 
+uint32_t grid_cap(uint32_t block) { return std::min<uint32_t>(0x7FFFFFFFu, 0xFFFFFFFFu / block); }
+
+uint32_t keys_grid(uint64_t work, const sq_launch_cfg& cfg, uint32_t cus) {
+  uint64_t grid = (uint64_t)cus * cfg.grid_per_cu;
+  const uint64_t need = (work + cfg.block - 1) / cfg.block;
+  if (grid > need || cfg.xcd_map == 2) grid = need;  // 2: one step per lane where the grid allows
+  grid = std::min<uint64_t>(grid, grid_cap(cfg.block));  // the kernels stride over what is left
+  return grid ? (uint32_t)grid : 1;  // the tail still needs a workgroup
+}
+
+uint32_t batch_grid(uint64_t tiles_bound, const sq_launch_cfg& cfg, uint32_t cus) {
+  const uint64_t grid = cfg.xcd_map == 2 ? tiles_bound : (uint64_t)cus * cfg.grid_per_cu;
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(grid, grid_cap(cfg.block)));
+}
+
 uint32_t max_segment_chunks(uint32_t block) {
-  // chunk indices and the grid stay below 2^31, and grid * block below 2^32
-  return std::min<uint32_t>(0x7FFFFFFFu, 0xFFFFFFFFu / block);
+  // one workgroup per chunk: chunk indices and the grid below 2^31, and
+  // grid * block below 2^32
+  return grid_cap(block);
 }
 
 void plan_fill(uint64_t nvec, const sq_launch_cfg& cfg, uint32_t cus, std::vector<FillSegment>& segs) {
@@ -1075,12 +1091,8 @@ hipError_t launch_keys(int kind, uint64_t ctr, const uint64_t* keys, uint64_t m,
   const int W = kind_bytes(kind), E = 16 / W;
   const bool vec = (((uintptr_t)keys | (uintptr_t)out) & 15) == 0;
   KeysArgs a{keys, (unsigned char*)out, m, ctr, vec ? m / E : 0};
-  const uint64_t work = vec ? a.nvec : m;
-  uint64_t grid = (uint64_t)device_info().cus * cfg.grid_per_cu;
-  const uint64_t need = (work + cfg.block - 1) / cfg.block;
-  if (grid > need || (cfg.xcd_map == 2 && need < (1ull << 31))) grid = need;  // 2: one step per lane
-  if (grid == 0) grid = 1;  // the tail still needs a workgroup
-  hipLaunchKernelGGL(keys_kernel(kind, vec), dim3((uint32_t)grid), dim3(cfg.block), 0, s, a);
+  const uint32_t grid = keys_grid(vec ? a.nvec : m, cfg, (uint32_t)device_info().cus);
+  hipLaunchKernelGGL(keys_kernel(kind, vec), dim3(grid), dim3(cfg.block), 0, s, a);
   return hipGetLastError();
 }
 
@@ -1228,12 +1240,12 @@ hipError_t launch_batch_body(const BatchDesc& d, const uint32_t* m_dev, void* ws
   if (e != hipSuccess) return e;
   // xcd_map 2: one tile per workgroup, grid = the bound on tiles of this
   // size (each stream has at most len / 2^lg + 1 of them, and the streams'
-  // outputs of at least 4 bytes fit the arena); workgroups past the scanned
-  // total exit at once.  Otherwise a persistent grid that takes tiles in a
-  // static interleave (0) or from the queue (1).
+  // outputs of at least 4 bytes fit the arena), capped below 2^32
+  // work-items (the kernel strides over tiles past the grid); workgroups
+  // past the scanned total exit at once.  Otherwise a persistent grid that
+  // takes tiles in a static interleave (0) or from the queue (1).
   const uint64_t tiles_bound = std::min<uint64_t>(max_tiles, (uint64_t)d.m + (d.out_bytes >> (cfg.tile_log2 + 2)) + 1);
-  const uint32_t grid = cfg.xcd_map == 2 ? (uint32_t)std::min<uint64_t>(tiles_bound, 0x7FFFFFFFull)
-                                         : (uint32_t)device_info().cus * cfg.grid_per_cu;
+  const uint32_t grid = batch_grid(tiles_bound, cfg, (uint32_t)device_info().cus);
   auto k = cfg.unroll == 1 ? k_batch_fill<1> : cfg.unroll == 2 ? k_batch_fill<2>
           : cfg.unroll == 4 ? k_batch_fill<4> : k_batch_fill<8>;
   hipLaunchKernelGGL(k, dim3(grid), dim3(cfg.block), 0, s, d, cfg.tile_log2, cfg.xcd_map, hdr,

@@ -112,6 +112,35 @@ def test_batch_stream_past_2p32_outputs(sq, oracle_mod):
     torch.cuda.empty_cache()
 
 
+def test_batch_one_tile_per_workgroup_grid_cap(sq, oracle_mod):
+    """One tile per workgroup with 4 KiB tiles and 1024-lane workgroups over a
+    16 GiB stream: the tile bound (2^22 + 2 tiles) times 1024 lanes passes
+    2^32 work-items, so the grid is capped and workgroups stride over the
+    remaining tiles.  The arena equals the
+    plain fill of the same stream, and its last 2^12 and 2^12 random outputs
+    equal the oracle's."""
+    import torch
+
+    n, key, ctr0 = (1 << 32) + 1000, 0x6A09E667F3BCC909, 0xBB67AE8584CAA73B
+    log(f"batch one tile per workgroup, grid cap: n={n}")
+    db = sq.batch_to_device(np.array([key], dtype=np.uint64), np.array([ctr0], dtype=np.uint64),
+                            np.array([n], dtype=np.uint64), np.array([0], dtype=np.uint64),
+                            np.array([0], dtype=np.uint8), 4 * n)
+    sq.fill_batch(db, launch_cfg=sq.cfg(block=1024, unroll=1, grid_per_cu=1, xcd_map=2, tile_log2=10))
+    assert sq.batch_errors(db) == 0
+    got = db.out[: 4 * n].view(torch.int32)
+    ref = sq.fill(0, key, ctr0, n).view(torch.int32)
+    assert torch.equal(got, ref)
+    del ref
+    g = np.random.Generator(np.random.PCG64(92))
+    idx = np.unique(np.concatenate([n - 1 - np.arange(1 << 12), g.integers(0, n, size=1 << 12)])).astype(np.int64)
+    vals = got[torch.from_numpy(idx).cuda()].cpu().numpy().view(np.uint32)
+    want = np.array([oracle_mod.fill(0, key, (ctr0 + int(i)) % 2**64, 1)[0] for i in idx], dtype=np.uint32)
+    assert np.array_equal(vals, want)
+    del db, got
+    torch.cuda.empty_cache()
+
+
 def test_per_stream_launches_equal_oracle_and_batch(sq, oracle_mod):
     """sq_fill_streams (one fill launch per stream, the batch's baseline)
     writes the oracle's arena, byte for byte the same as sq_fill_batch, for

@@ -263,12 +263,38 @@ def test_full_size_complete(sq, oracle_mod, kind):
     torch.cuda.empty_cache()
 
 
-def test_fill_2p33_u64_in_two_launches(sq, oracle_mod):
+def test_fill_past_2p31_work_items(sq, oracle_mod):
+    """n = 2^32 + 2^30 U64 outputs (40 GiB) in the default shape: one launch of
+    10485760 workgroups of 256 lanes (2.7e9 work-items, past 2^31 and below
+    the 2^32 a launch may hold).  The outputs around output 2^31 + 2^29, the
+    first and last 2^14 and 2^12 random positions equal the oracle's."""
+    import torch
+
+    key, ctr0 = 0xC2B2AE3D27D4EB4F, 0x165667B19E3779F9
+    n, k = (1 << 32) + (1 << 30), 1 << 14
+    log(f"fill U64 n=2^32+2^30 key={key:#x} ctr0={ctr0:#x}")
+    out = sq.fill(2, key, ctr0, n)
+    mid = n // 2
+    for a in (0, mid - k, n - k):
+        got = out[a: a + (2 * k if a == mid - k else k)].cpu().numpy()
+        ref = oracle_mod.fill(2, key, (ctr0 + a) % 2**64, got.size, threads=HOST_THREADS)
+        assert np.array_equal(got, ref), f"block at {a}"
+    g = np.random.Generator(np.random.PCG64(2032))
+    idx = g.integers(0, n, size=1 << 12)
+    got = out.view(torch.int64)[torch.from_numpy(idx.astype(np.int64)).cuda()].cpu().numpy().view(np.uint8)
+    for row, i in zip(got.reshape(-1, 8), idx):
+        assert row.tobytes() == oracle_element(oracle_mod, 2, key, ctr0, int(i)), f"position {int(i)}"
+    del out
+    torch.cuda.empty_cache()
+
+
+def test_fill_2p33_u64_split_launches(sq, oracle_mod):
     """n = 2^33 U64 outputs (64 GiB) in the default shape (one 4 KiB chunk per
     256-lane workgroup) needs 2^24 workgroups, more than one launch of fewer
     than 2^32 work-items can hold, so the fill is split into two launches of
-    2^23 chunks.  The 2^15 outputs around the boundary (output 2^32), the
-    first and last 2^14 and 2^12 random positions equal the oracle's."""
+    2^23 chunks.  The 2^15 outputs around
+    output 2^32, the first and last 2^14 and 2^12 random positions equal the
+    oracle's."""
     import torch
 
     from paper_2004_06278_amd import workloads as W

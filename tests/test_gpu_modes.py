@@ -306,6 +306,34 @@ def test_make_keys_and_key_counter_past_2p32(sq, oracle_mod):
     torch.cuda.empty_cache()
 
 
+def test_key_counter_grid_cap(sq, oracle_mod):
+    """2^33 + 3 squares64 keys generated on the device (2^32 + 1 vectors of two
+    outputs, 64 GiB of keys and 64 GiB of output) with one vector per lane
+    asked for: one workgroup per 256 vectors would be 2^32 + 256 work-items,
+    more than a launch may hold, so the grid is capped (16777215 workgroups)
+    and the kernel strides over the rest.  At the last 2^12 and 2^12 random positions the
+    keys equal the oracle's key generation and the outputs the oracle's
+    key-counter mode."""
+    import torch
+
+    gk, c0, ctr = 0x13198A2E03707344, 0xA4093822299F31D0, 0x5851F42D4C957F2D
+    m = (1 << 33) + 3
+    log(f"key-counter grid cap m={m}")
+    keys = sq.make_keys(gk, c0, m)
+    out = sq.fill_keys(2, ctr, keys, launch_cfg=sq.cfg(256, 1, 1, 2))
+    g = np.random.Generator(np.random.PCG64(78))
+    idx = np.unique(np.concatenate([m - 1 - np.arange(1 << 12), g.integers(0, m, size=1 << 12)])).astype(np.int64)
+    ti = torch.from_numpy(idx).cuda()
+    got_k = keys.view(torch.int64)[ti].cpu().numpy().view(np.uint64)
+    got_o = out.view(torch.int64)[ti].cpu().numpy().view(np.uint64)
+    for j in (int(idx[0]), int(idx[len(idx) // 2]), int(idx[-1])):
+        k = got_k[np.searchsorted(idx, j)]
+        assert k == oracle_mod.make_keys(gk, (c0 + 2 * j) % 2**64, 1)[0], f"key {j}"
+    assert np.array_equal(got_o, oracle_mod.fill_keys(2, ctr, got_k))
+    del keys, out
+    torch.cuda.empty_cache()
+
+
 def test_scalar_entry_points_paper_argument_order(sq, oracle_mod):
     """sq32_at / sq64_at take (ctr, key) like the paper's functions and agree
     with the oracle and with element 0 of a bulk fill called as (key, ctr0)."""
