@@ -205,6 +205,30 @@ def test_transcription_int128_every_round(oracle_mod, tmp_path):
     assert np.array_equal(got, want)
 
 
+def test_oracle_under_host_sanitizers(tmp_path):
+    """Every oracle entry point on edge cases with buffers of exactly the size
+    each call may write, built with gcc's address and undefined-behaviour
+    sanitizers (tests/oracle_sanitize.c): no out-of-range access, no
+    undefined shift or overflow, no leak, and the entry points agree with
+    each other.  Skipped where the host compiler has no sanitizer runtime."""
+    import os
+    import subprocess
+
+    here = os.path.dirname(os.path.abspath(__file__))
+    exe = str(tmp_path / "oracle_sanitize")
+    cmd = ["gcc", "-std=c11", "-O1", "-g", "-Wall", "-Wextra", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", os.path.join(here, "oracle_sanitize.c"),
+           os.path.join(here, "..", "oracle", "squares_oracle.c"), "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        if "asan" in r.stderr or "ubsan" in r.stderr:
+            pytest.skip("no sanitizer runtime for the host compiler")
+        pytest.fail(r.stderr)
+    run = subprocess.run([exe], capture_output=True, text=True, timeout=300,
+                         env=dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0"))
+    assert run.returncode == 0 and run.stdout.strip().endswith("ok"), run.stdout[-2000:] + run.stderr[-2000:]
+
+
 # ---------------------------------------------------------------- bulk: counters
 def test_fill_is_counter_order(oracle_mod):
     o = oracle_mod
