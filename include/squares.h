@@ -98,7 +98,9 @@ double sq_u128_to_double_scaled(uint64_t lo, uint64_t hi, int pow2_exp);
  * SQ_EALIGN; 16-byte alignment is not required (elements up to the first
  * 1 KiB boundary and after the last full 16-byte vector are written one by
  * one).  n == 0 returns SQ_OK without a launch; a
- * null `out` with n > 0 is SQ_EINVAL.  out must hold n elements.
+ * null `out` with n > 0 is SQ_EINVAL.  out must hold n elements.  Any n
+ * is accepted: a fill whose grid would reach 2^32 work-items is issued as
+ * several launches on the same stream.
  * ------------------------------------------------------------------------ */
 int sq32_fill(uint64_t key, uint64_t ctr0, uint64_t n, uint32_t *out, void *stream);
 int sq64_fill(uint64_t key, uint64_t ctr0, uint64_t n, uint64_t *out, void *stream);
@@ -260,8 +262,9 @@ int sq_reduce_strided_cfg(sq_kind kind, uint64_t key, uint64_t ctr0, uint64_t st
  * works one element per lane.  m == 0 returns SQ_OK without a launch.  The
  * _cfg variant takes `block`, `grid_per_cu` and `xcd_map` from cfg
  * (validated as a fill configuration; xcd_map 2 launches one workgroup per
- * block of work instead of a grid-stride loop; `unroll` and `tile_log2` are
- * ignored).
+ * block of work instead of a grid-stride loop, as far as a grid below 2^32
+ * work-items reaches, and the workgroups stride over the rest; `unroll` and
+ * `tile_log2` are ignored).
  * ------------------------------------------------------------------------ */
 int sq_fill_keys(sq_kind kind, uint64_t ctr, const uint64_t *keys, uint64_t m, void *out,
                  void *stream);
