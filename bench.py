@@ -132,14 +132,23 @@ def run_metadata(torch) -> dict:
     """Where and on what the line was measured."""
     import subprocess
 
-    rev = None
+    rev, source = None, None
     try:
         rev = subprocess.run(["git", "-C", ROOT, "rev-parse", "--short=12", "HEAD"], capture_output=True, text=True,
                              timeout=10).stdout.strip() or None
+        source = "checkout" if rev else None
     except (OSError, subprocess.SubprocessError):
         pass
+    if rev is None:  # no checkout here: the revision the library was built from
+        try:
+            with open(os.path.join(ROOT, "paper_2004_06278_amd", "build_info.json")) as f:
+                info = json.load(f)
+            rev = info.get("git_rev")
+            source = "library build" + (" (tree had changes)" if info.get("tree_had_changes") else "")
+        except (OSError, ValueError):
+            pass
     prop = torch.cuda.get_device_properties(0)
-    return {"git_rev": rev, "kernel_source_sha": kernel_source_sha(), "device": prop.name,
+    return {"git_rev": rev, "git_rev_source": source, "kernel_source_sha": kernel_source_sha(), "device": prop.name,
             "gfx_arch": getattr(prop, "gcnArchName", None), "cus": prop.multi_processor_count,
             "hip": getattr(torch.version, "hip", None), "torch": torch.__version__}
 

@@ -46,7 +46,30 @@ def build(verbose: bool = False) -> str:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("hipcc link failed")
     os.replace(tmp, LIB)
+    write_build_info()
     return LIB
+
+
+BUILD_INFO = os.path.join(HERE, "build_info.json")
+
+
+def write_build_info() -> None:
+    """Records next to the library the git revision it was built from (and
+    whether the tree had changes), for run records made where no git
+    checkout is present."""
+    import json
+
+    rev, dirty = None, None
+    try:
+        rev = subprocess.run(["git", "-C", HERE, "rev-parse", "--short=12", "HEAD"], capture_output=True, text=True,
+                             timeout=10).stdout.strip() or None
+        if rev:
+            dirty = bool(subprocess.run(["git", "-C", HERE, "status", "--porcelain", "--untracked-files=no"],
+                                        capture_output=True, text=True, timeout=10).stdout.strip())
+    except (OSError, subprocess.SubprocessError):
+        pass
+    with open(BUILD_INFO, "w") as f:
+        json.dump({"git_rev": rev, "tree_had_changes": dirty}, f)
 
 
 def build_calib(verbose: bool = False) -> str:
