@@ -125,6 +125,46 @@ def test_fill_lanes_shape_ragged_misaligned(sq, oracle_mod, kind):
     torch.cuda.empty_cache()
 
 
+def test_fill_and_reduce_replayed_from_a_captured_graph(sq, oracle_mod):
+    """A squares32 fill large enough for the lane-table kernel (its lane
+    offsets travel in the kernel arguments), a small squares64 fill and a
+    fused F64 sum, captured once into a HIP graph and replayed three times
+    with eager work and synchronisations in between: every replay equals the
+    eager result, which equals the oracle's."""
+    import torch
+
+    key, ctr0 = 0x8F1BBCDCCA62C1D6, 2**64 - 3000
+    n_big, n_small, n_sum = (1 << 24) + 5, 10007, 1 << 20
+    ref_big = sq.fill(0, key, ctr0, n_big)
+    ref_small = sq.fill(2, key, ctr0, n_small)
+    ref_sum = sq.reduce(3, key, ctr0, n_sum)
+    assert np.array_equal(ref_big.cpu().numpy().view(np.uint32),
+                          oracle_mod.fill(0, key, ctr0, n_big, threads=HOST_THREADS))
+    assert np.array_equal(ref_small.cpu().numpy().view(np.uint64), oracle_mod.fill(2, key, ctr0, n_small))
+    big = torch.zeros_like(ref_big)
+    small = torch.zeros_like(ref_small)
+    res = sq.result_tensor()
+    ws = sq.reduce_workspace(n_sum)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        sq.fill(0, key, ctr0, n_big, out=big)
+        sq.fill(2, key, ctr0, n_small, out=small)
+        sq.reduce_async(3, key, ctr0, n_sum, res, ws)
+    for r in range(3):
+        log(f"graph replay {r}")
+        big.zero_()
+        small.zero_()
+        res.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(big, ref_big), f"replay {r}: lane-table fill"
+        assert torch.equal(small, ref_small), f"replay {r}: small fill"
+        assert sq.read_result(res) == ref_sum, f"replay {r}: sum"
+    del g, big, small
+
+
 def test_invalid_arguments(sq):
     import torch
 
