@@ -128,25 +128,32 @@ def measure_lib():
     return L
 
 
-def run_metadata(torch) -> dict:
-    """Where and on what the line was measured."""
+def git_revision(root: str = ROOT) -> tuple[str | None, str | None]:
+    """(revision, where it came from): the checkout's HEAD, else the revision
+    the library build recorded in build_info.json (runs made where the tree
+    was copied without its git history), else (None, None)."""
     import subprocess
 
-    rev, source = None, None
     try:
-        rev = subprocess.run(["git", "-C", ROOT, "rev-parse", "--short=12", "HEAD"], capture_output=True, text=True,
-                             timeout=10).stdout.strip() or None
-        source = "checkout" if rev else None
+        rev = subprocess.run(["git", "-C", root, "rev-parse", "--short=12", "HEAD"], capture_output=True, text=True,
+                             timeout=10).stdout.strip()
+        if rev:
+            return rev, "checkout"
     except (OSError, subprocess.SubprocessError):
         pass
-    if rev is None:  # no checkout here: the revision the library was built from
-        try:
-            with open(os.path.join(ROOT, "paper_2004_06278_amd", "build_info.json")) as f:
-                info = json.load(f)
-            rev = info.get("git_rev")
-            source = "library build" + (" (tree had changes)" if info.get("tree_had_changes") else "")
-        except (OSError, ValueError):
-            pass
+    try:
+        with open(os.path.join(root, "paper_2004_06278_amd", "build_info.json")) as f:
+            info = json.load(f)
+    except (OSError, ValueError):
+        return None, None
+    if not info.get("git_rev"):
+        return None, None
+    return info["git_rev"], "library build" + (" (tree had changes)" if info.get("tree_had_changes") else "")
+
+
+def run_metadata(torch) -> dict:
+    """Where and on what the line was measured."""
+    rev, source = git_revision()
     prop = torch.cuda.get_device_properties(0)
     return {"git_rev": rev, "git_rev_source": source, "kernel_source_sha": kernel_source_sha(), "device": prop.name,
             "gfx_arch": getattr(prop, "gcnArchName", None), "cus": prop.multi_processor_count,

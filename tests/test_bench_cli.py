@@ -89,3 +89,20 @@ def test_clock_from_samples():
     raw = np.stack([clk, wall], axis=1).reshape(-1)
     c = bench.clock_from_samples(raw)
     assert c["mean_ghz"] == 2.0 and c["p10_ghz"] == 2.0 and c["samples"] == 100
+
+
+def test_git_revision_falls_back_to_the_build_record(tmp_path):
+    """Outside a git checkout the revision comes from the library build's
+    build_info.json; without either it is unknown."""
+    import json
+
+    import bench
+
+    assert bench.git_revision(str(tmp_path)) == (None, None)
+    (tmp_path / "paper_2004_06278_amd").mkdir()
+    with open(tmp_path / "paper_2004_06278_amd" / "build_info.json", "w") as f:
+        json.dump({"git_rev": "0123456789ab", "tree_had_changes": True}, f)
+    assert bench.git_revision(str(tmp_path)) == ("0123456789ab", "library build (tree had changes)")
+    if os.path.isdir(os.path.join(bench.ROOT, ".git")):
+        rev, source = bench.git_revision()
+        assert source == "checkout" and rev
