@@ -316,11 +316,6 @@ __device__ __forceinline__ uint64_t sum_term_after1(uint64_t r1, uint64_t y, uin
   }
 }
 
-template <int K>
-__device__ __forceinline__ uint64_t sum_term(uint64_t y, uint64_t z) {
-  return sum_term_after1<K>(square_plus(y, y), y, z);
-}
-
 // The low-half term of a split kind (the last element of an odd count).
 template <int K>
 __device__ __forceinline__ uint64_t split_lo_term(uint64_t y, uint64_t z) {
