@@ -44,6 +44,15 @@ __global__ void k_rate(uint64_t* out, unsigned long long* clk, int iters, uint32
       if (OP == 2) x[j] = x[j] * y[j];                                                   // v_mul_lo_u32
       if (OP == 3) w[j] = w[j] + (uint64_t)y[j];                                         // v_lshl_add_u64
       if (OP == 4) asm volatile("v_lshl_add_u32 %0, %0, 1, %1" : "+v"(x[j]) : "v"(y[j]));
+      if (OP == 5) asm volatile("v_mul_hi_u32 %0, %0, %1" : "+v"(x[j]) : "v"(y[j]));
+      if (OP == 6) asm volatile("v_add_co_u32_e32 %0, vcc, %0, %1" : "+v"(x[j]) : "v"(y[j]) : "vcc");
+      if (OP == 7) asm volatile("v_lshrrev_b32_e32 %0, 3, %0" : "+v"(x[j]));
+      // the conversions and float ops read the registers' bits as whatever
+      // they encode; only the issue rate is measured
+      if (OP == 8) asm volatile("v_cvt_f32_u32_e32 %0, %0" : "+v"(x[j]));
+      if (OP == 9) asm volatile("v_mul_f32_e32 %0, %0, %1" : "+v"(x[j]) : "v"(y[j]));
+      if (OP == 10) asm volatile("v_cvt_f64_u32_e32 %0, %1" : "=v"(w[j]) : "v"(x[j]));
+      if (OP == 11) asm volatile("v_fma_f64 %0, %0, %0, %0" : "+v"(w[j]));
     }
   }
   const unsigned long long c1 = clock64(), t1 = wall_clock64();
@@ -134,6 +143,13 @@ int main() {
   rate<1>("v_mad_u64_u32", cus, out, clk, hclk);
   rate<2>("v_mul_lo_u32", cus, out, clk, hclk);
   rate<3>("64-bit add", cus, out, clk, hclk);
+  rate<5>("v_mul_hi_u32", cus, out, clk, hclk);
+  rate<6>("v_add_co_u32", cus, out, clk, hclk);
+  rate<7>("v_lshrrev_b32", cus, out, clk, hclk);
+  rate<8>("v_cvt_f32_u32", cus, out, clk, hclk);
+  rate<9>("v_mul_f32", cus, out, clk, hclk);
+  rate<10>("v_cvt_f64_u32", cus, out, clk, hclk);
+  rate<11>("v_fma_f64", cus, out, clk, hclk);
   CK(hipFree(out));
   CK(hipFree(clk));
   std::free(hclk);
